@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Benchmark of the all-pairs binary-star step on one MI355X.
+
+Default workload: two-star system of N = 262,144 elements (q = 0.3, PCG64 seed 0), FP32 forces with
+Kahan-compensated accumulation, dt = 1e-4, donor growth and the L1 count every step. A step is
+one full kick-drift-kick leap-frog step (O(N^2) force evaluation plus the O(N) kicks, drift,
+growth update and L1 count), all in libnbody's HIP kernels, with the state resident in HBM.
+
+Prints ONE JSON line: interactions/s over the timed steps (N^2 per step), the force kernel's
+roofline position (20 flops per interaction, measured with HIP events on the launch stream) and
+the FP64 CPU oracle's rate on a bounded row sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--workload c3|c2|c4] [--mode kahan|plain|fp64]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "pair interactions/s + % FP32 VALU peak at N=256K; served sims/s, p50/p99"
+FLOPS_PER_INTERACTION = 20
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 (packed FP32) x 2 (FMA) x 2.4 GHz
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_UNPACKED_TFLOPS = PEAK_FP32_TFLOPS / 2
+PEAK_FP64_TFLOPS = 78.6
+
+WORKLOADS = {
+    "c3": dict(n=262144, q=0.3, mode="kahan", steps=200, warmup=5),
+    "c2": dict(n=65536, q=0.5, mode="kahan", steps=1000, warmup=10),
+    "c4": dict(n=131072, q=0.8, mode="kahan", steps=200, warmup=5),
+}
+
+KERNEL_NAMES = {"kahan": "k_force_f32<2,true>", "plain": "k_force_f32<2,false>",
+                "fp64": "k_force_f64"}
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "force_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2303_12166_amd", "csrc", "nb_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def hbm_traffic(workload: str, mode: str):
+    """HBM bytes per force launch from committed rocprofv3 counters, if they match this source."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    entry = rec.get("%s:%s" % (workload, mode))
+    if not entry or entry.get("kernel_sha") != kernel_source_sha():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def cpu_baseline(ic, target_seconds: float):
+    """The FP64 oracle on a bounded row sample of the same workload (one force evaluation)."""
+    import numpy as np
+
+    import oracle
+
+    p, _ = ic.f32_as_f64()
+    n = ic.n
+    cores = oracle.max_threads()
+    # calibrate on a short sample (second pass: threads already running)
+    cal_rows = np.linspace(0, n - 1, 4 * cores).astype(np.int64)
+    for _ in range(2):
+        t0 = time.perf_counter()
+        oracle.accel(p, ic.n1, ic.G, ic.m, ic.D1, ic.D2, rows=cal_rows)
+        t_cal = max(time.perf_counter() - t0, 1e-6)
+    rate = len(cal_rows) * n / t_cal
+    k = int(min(n, max(64, target_seconds * rate / n)))
+    rows = np.linspace(0, n - 1, k).astype(np.int64)
+    t0 = time.perf_counter()
+    ref = oracle.accel(p, ic.n1, ic.G, ic.m, ic.D1, ic.D2, rows=rows)
+    t = time.perf_counter() - t0
+    return {
+        "value": k * n / t,
+        "unit": "interactions/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": "%d of %d rows, each against all %d elements (one FP64 force evaluation "
+                  "of the step-0 state, %.1f s)" % (k, n, n, t),
+        "cpu": cpu_model(),
+    }, rows, ref
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c3")
+    ap.add_argument("--mode", choices=["kahan", "plain", "fp64"], default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2303_12166_amd as nb
+    import synth
+
+    wl = WORKLOADS[args.workload]
+    mode = args.mode or wl["mode"]
+    steps = wl["steps"] if args.steps is None else args.steps
+    warmup = wl["warmup"] if args.warmup is None else args.warmup
+    n, q = wl["n"], wl["q"]
+
+    nb.load()
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        return 1
+    torch.cuda.set_device(0)
+    log("workload %s: N=%d q=%.2f mode=%s steps=%d warmup=%d" % (args.workload, n, q, mode, steps,
+                                                                  warmup))
+    ic = synth.make_binary(n, q, seed=0)
+    s = nb.System.from_ic(ic, mode=mode, dt=1e-4)
+    a0 = s.accelerations()
+    cfg = nb.nb_tile_config(n, nb.MODES[mode])
+    log("tile config", cfg)
+
+    s.step(warmup)
+    s.synchronize()
+    nb.nb_timing_reset()
+    nb.nb_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.step(1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nb.nb_timing_enable(False)
+    force_ms, launches = nb.nb_timing_read()
+    elapsed = t1 - t0
+    d = s.diagnostics(with_pe=False)
+    log("timed %d steps in %.3f s; force kernel %.3f ms avg over %d launches" %
+        (steps, elapsed, force_ms / max(launches, 1), launches))
+
+    inter = float(n) * float(n)
+    value = inter * steps / elapsed
+    avg_s = force_ms / max(launches, 1) / 1e3
+    peak = PEAK_FP64_TFLOPS if mode == "fp64" else PEAK_FP32_TFLOPS
+    achieved = FLOPS_PER_INTERACTION * inter / avg_s / 1e12 if avg_s > 0 else 0.0
+    roofline = {
+        "bound": "alu",
+        "achieved": round(achieved, 3),
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": round(achieved / peak, 4),
+        "traffic": hbm_traffic(args.workload, mode),
+        "kernel": KERNEL_NAMES[mode],
+        "avg_launch_ms": round(avg_s * 1e3, 4),
+        "launches": launches,
+        "flops_per_launch": FLOPS_PER_INTERACTION * inter,
+        "kernel_interactions_per_s": inter / avg_s if avg_s > 0 else 0.0,
+    }
+    if mode != "fp64":
+        roofline["frac_of_unpacked_fp32_peak"] = round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": elapsed / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if mode == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "two-star binary, N=%d, q=%g, %s forces, dt=1e-4, donor growth + L1 "
+                        "count every step" % (n, q, {"kahan": "FP32 Kahan", "plain": "FP32 plain",
+                                                       "fp64": "FP64"}[mode]),
+            "n": n,
+            "q": q,
+            "mode": mode,
+            "seed": 0,
+            "tile": cfg,
+        },
+        "roofline": roofline,
+        "state_after": {"step": d["step"], "n_past_L1": d["n_past_L1"], "D2": d["D2"],
+                        "nonfinite": d["nonfinite"]},
+    }
+    s.close()
+
+    if not args.no_cpu:
+        base, rows, ref = cpu_baseline(ic, args.cpu_seconds)
+        out["cpu_baseline"] = base
+        err = (np.linalg.norm(a0[rows] - ref, axis=1).max() / np.linalg.norm(ref, axis=1).max())
+        out["force_error_step0"] = {"value": float(err), "rows": int(len(rows)),
+                                    "metric": "max_i |a_gpu-a_oracle| / max_k |a_oracle|"}
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,160 @@
+/*
+ * nbody.h -- C ABI of libnbody, the MI355X (gfx950) library for the gravity-centred binary-star
+ * element model of Goderya et al., "N-body simulation of binary star mass transfer using NVIDIA
+ * GPUs".
+ *
+ * The model (Methodology section): a star is a ball of N elements of one common mass and one
+ * common diameter; every element's motion comes only from the sum of all pairwise
+ * element-element interactions. Elements always attract; elements in contact also repel. The
+ * contact law implemented here is the conservative one
+ *     f(r) = G m^2 / r^2                       r >= D
+ *     f(r) = G m^2 r / D^3 - K (1 - r/D)       r <  D,   K = 10 G m^2 / D^2
+ * (f > 0 attracts), with D the element diameter of the pair: D1 inside star 1, D2 inside star 2,
+ * (D1 + D2)/2 across. Time stepping is the leap-frog integrator (Methodology) in kick-drift-kick
+ * form. The donor (star 2) expands by growing its element diameter until its radius reaches the
+ * Roche-lobe radius of eq. (3); elements of the donor crossing the plane through L1 are counted
+ * every step.
+ *
+ * Conventions shared by every entry point
+ *  - Status: 0 = NB_OK; negative values are errors (nb_strerror names them). No exception or
+ *    signal crosses the ABI; invalid arguments are reported, never dereferenced.
+ *  - Device memory is owned by the caller (for example PyTorch tensors, passed as data
+ *    pointers). The library never frees it. It keeps only host-side structs and HIP events.
+ *    Multi-system steps additionally use one small library-owned device table (segment table).
+ *  - Streams are `hipStream_t` values passed as `void *` (NULL = the default stream). Every call
+ *    on a system is ordered on the stream it is given; calls on different systems may run
+ *    concurrently on different streams.
+ *  - Layout: structure of arrays. x, y, z, vx, vy, vz, ax, ay, az are n contiguous elements each
+ *    (float for the FP32 modes, double for NB_FP64). Star 1 (the accretor, mass 1) owns indices
+ *    [0, n1), star 2 (the donor, mass q) owns [n1, n).
+ *  - A system's buffers must not be used by another system at the same time.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define NB_OK 0
+#define NB_E_INVAL (-1)     /* bad argument: null pointer, size, mode, misaligned buffer */
+#define NB_E_HIP (-2)       /* a HIP runtime call failed */
+#define NB_E_NOMEM (-3)     /* scratch smaller than nb_scratch_bytes, or a library table failed */
+#define NB_E_NONFINITE (-4) /* a position or velocity became NaN or infinite */
+#define NB_E_MISMATCH (-5)  /* systems of different precision modes in one multi-system call */
+
+/* precision modes of the force evaluation */
+#define NB_FP32_PLAIN 0 /* FP32, one running sum per element over all j in order */
+#define NB_FP32_KAHAN 1 /* FP32 tile partials, compensated (Kahan) sum across tiles */
+#define NB_FP64 2       /* FP64 throughout (reference mode) */
+
+typedef struct nb_system nb_system; /* opaque, host-side, owned by the library */
+
+/* Physical and numerical parameters of one two-star system. */
+typedef struct {
+    int64_t n;           /* elements, 0 <= n < 2^31 */
+    int64_t n1;          /* elements of star 1, 0 <= n1 <= n */
+    double G;            /* gravitational constant */
+    double m;            /* common element mass */
+    double dt;           /* leap-frog time step */
+    double D1, D2;       /* element diameters of star 1 and star 2 at t = 0 (> 0) */
+    double q;            /* mass ratio m2/m1 used by eq. (3) and for L1 (> 0) */
+    double a;            /* nominal separation; the donor stops growing at r_L(q) a */
+    double R2_0;         /* donor radius at t = 0; its radius is R2_0 D2 / D2(t=0) */
+    double growth_rate;  /* D2 <- D2 (1 + growth_rate) per step while growing */
+    int32_t growth_on;   /* 0: the donor never grows */
+    int32_t mode;        /* NB_FP32_PLAIN, NB_FP32_KAHAN or NB_FP64 */
+} nb_params;
+
+/* Device buffers of one system (caller-owned, see the conventions above). */
+typedef struct {
+    void *x, *y, *z;     /* positions (inout), n elements each */
+    void *vx, *vy, *vz;  /* velocities (inout) */
+    void *ax, *ay, *az;  /* accelerations (out; valid after nb_create) */
+    void *side;          /* n bytes: per-element L1 side flag (library-written) */
+    void *scratch;       /* workspace, 256-byte aligned, at least nb_scratch_bytes() */
+    size_t scratch_bytes;
+} nb_buffers;
+
+/* FP64 diagnostics of one system, read back by nb_diagnostics. */
+typedef struct {
+    double com[3];       /* centre of mass */
+    double P[3];         /* linear momentum, sum m v */
+    double L[3];         /* angular momentum about the origin, sum m r x v */
+    double KE, PE, E;    /* kinetic, potential (0 unless requested) and total energy */
+    double D2, R2;       /* current donor element diameter and nominal donor radius */
+    int64_t step;        /* completed leap-frog steps */
+    int32_t n_past_L1;   /* donor elements past the L1 plane after the last step */
+    int32_t cross_fwd;   /* donor elements that crossed toward the accretor in the last step */
+    int32_t cross_bwd;   /* donor elements that crossed back in the last step */
+    int32_t growth_stopped; /* 1 once the donor has reached its Roche lobe */
+    int32_t nonfinite;   /* elements with a non-finite position or velocity (last step) */
+    int32_t pad;
+} nb_diag;
+
+/* Bytes of device workspace (`scratch`) a system with these parameters needs. Depends only on
+ * n, n1 and mode. Returns NB_E_INVAL for invalid parameters. */
+int nb_scratch_bytes(const nb_params *p, size_t *out);
+
+/* Validates p and b, lays out the workspace, initialises the device state (FP64 diameters and
+ * growth flag, derived FP32 force constants), sets every donor element's L1 side from the
+ * initial positions and evaluates the initial accelerations a(x0) into ax/ay/az, all ordered on
+ * `stream`, which it synchronises before returning. On success *out owns a new handle (free with
+ * nb_destroy). On error *out is NULL and nothing needs freeing. */
+int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system **out);
+
+/* One all-pairs evaluation (Methodology: the sum of every pairwise interaction):
+ * a_i = sum_{j != i} (f(r_ij) / m) (r_j - r_i) / r_ij with the current diameters, written to
+ * ax/ay/az. Asynchronous on `stream`. */
+int nb_forces(nb_system *s, void *stream);
+
+/* Advances every listed system by n_steps leap-frog steps (Methodology: leap-frog integrator):
+ * v += a dt/2; x += v dt; a = F(x); v += a dt/2; then the donor growth update (diameter grows by
+ * (1 + growth_rate) while R2_0 D2/D2_0 <= r_L(q) a, eq. 3; the first step that finds it larger
+ * stops growth for good) and the L1 count. n_sys = 1 is the plain path. With n_sys > 1 all
+ * systems advance together: each kernel of a step is one launch over all systems' work (a
+ * segment table), and each system's results are bitwise the same as when it runs alone. The
+ * systems must share one mode and must be distinct. Asynchronous on `stream`. */
+int nb_step(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *stream);
+
+/* FP64 diagnostics: centre of mass, momentum, angular momentum, kinetic energy, and with
+ * with_pe != 0 the potential energy sum_{i<j} U(r_ij) (U continuous with dU/dr = f; O(n^2)).
+ * Synchronises `stream` and fills *out. Returns NB_E_NONFINITE (after filling *out) if the last
+ * step saw a non-finite element. */
+int nb_diagnostics(nb_system *s, int32_t with_pe, nb_diag *out, void *stream);
+
+/* Per-step L1 record of the most recent steps: up to max_steps rows of
+ * {step, n_past, forward, backward}, oldest first, into out_host (int32, 4 per row). The library
+ * keeps the last NB_L1_LOG_CAP steps. Synchronises `stream`. *n_out receives the row count. */
+#define NB_L1_LOG_CAP 4096
+int nb_l1_log(nb_system *s, int32_t *out_host, int32_t max_steps, int32_t *n_out, void *stream);
+
+/* Force-kernel timing: while enabled, every force launch issued by nb_forces/nb_step is
+ * bracketed by HIP events on its stream. nb_timing_read synchronises those events and returns
+ * the summed kernel time (ms) and launch count since the last reset. */
+int nb_timing_enable(int32_t on);
+int nb_timing_read(double *total_ms, int64_t *launches);
+int nb_timing_reset(void);
+
+/* Tile configuration chosen for a system of n elements in a mode: elements per lane (ki), j
+ * chunks per i-block (nsplit), i-block size and chunk length. Depends only on (n, mode). */
+int nb_tile_config(int64_t n, int32_t mode, int32_t *ki, int32_t *nsplit, int32_t *iblock,
+                   int32_t *jchunk);
+
+/* Overrides the split choice for systems created afterwards whose n lies in [n_lo, n_hi]
+ * (nsplit = 0 restores the built-in rule). Used by the autotuner. */
+int nb_tile_override(int64_t n_lo, int64_t n_hi, int32_t nsplit);
+
+void nb_destroy(nb_system *s);
+const char *nb_strerror(int status);
+int nb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBODY_H */

@@ -1,0 +1,82 @@
+// nb_internal.h -- device-side data structures shared by the HIP kernels and the C++ runtime of
+// libnbody. Not part of the public ABI (include/nbody.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nbk {
+
+constexpr int BT = 256;          // threads per block, every kernel
+constexpr int TJ = 256;          // j elements staged in LDS per tile (one per thread)
+constexpr int KI32 = 2;          // i elements per lane, FP32 force kernel
+constexpr int KI64 = 1;          // i elements per lane, FP64 force kernel
+constexpr int RED_STRIDE = 32;   // doubles per O(N)-unit partial record
+constexpr int RED_STEP = 0;      // record slots [0, 16): per-step sums (COMs, flags, L1 counts)
+constexpr int RED_DIAG = 16;     // record slots [16, 32): diagnostics sums
+constexpr int L1_LOG_CAP = 4096; // rows of the per-step L1 log
+constexpr float SENTINEL_F32 = 1.0e18f;  // position of padding j elements (contributes exactly 0)
+
+// Pair classes: 0 = star 1 with star 1, 1 = across the stars, 2 = star 2 with star 2.
+
+// Per-system state that lives in device memory (first bytes of the system's workspace).
+struct alignas(16) DevState {
+    // FP64 masters
+    double D1, D2, D2_0, R2_0, rL_a, growth_rate;
+    double G, m, dt, xi_l1;
+    double c1d[3], c2d[3];   // 11 / D^3 and 10 / D^2 per pair class
+    double gm_d, h_d;        // G m and dt / 2
+    // L1 plane of the current step
+    double com1[3], com2[3], e[3], xi_cut;
+    // FP32 copies used by the FP32 kernels
+    float c1f[3], c2f[3];
+    float gm_f, h_f, dt_f, pad_f;
+    int64_t step;
+    int32_t growth_on, growth_stopped;
+    int32_t n_past, fwd, bwd, nonfinite;
+    int32_t plane_ok, pad_i;
+};
+
+struct DiagOut {
+    double v[16];  // com[3], P[3], L[3], KE, PE
+};
+
+// One entry of a launch's segment table.
+struct SysDesc {
+    void *x, *y, *z, *vx, *vy, *vz, *ax, *ay, *az;
+    int8_t *side;
+    DevState *st;
+    void *part;         // j-split partial sums, nsplit * 3 * n values (nsplit > 1 only)
+    double *red;        // n_ounits * RED_STRIDE doubles
+    double *pe_part;    // n_peunits doubles
+    int32_t *l1_log;    // L1_LOG_CAP * 4 int32
+    DiagOut *diag;
+    int32_t n, n1;
+    int32_t nsplit, jchunk;     // j chunks per i-block and chunk length (multiple of TJ)
+    int32_t iblock, n_iblocks;  // i elements per block (BT * ki) and block count
+    int32_t n_units, n_ounits;  // force units (n_iblocks * nsplit) and O(N) units (ceil(n / BT))
+    int32_t unit_begin, ounit_begin;  // prefix offsets in the launch's segment table
+    int32_t n_peunits, pad;
+};
+
+// Kernel argument describing one launch over a segment table.
+struct Launch {
+    const SysDesc *sys;
+    int32_t n_sys;
+    int32_t total_units;
+    int32_t total_ounits;
+    int32_t pad;
+};
+
+// Host-side launchers (nb_kernels.hip). All return the HIP status of the launch.
+hipError_t launch_init_state(DevState *st, const DevState &init, hipStream_t s);
+hipError_t launch_forces(const Launch &L, int mode, hipStream_t s);
+hipError_t launch_combine(const Launch &L, int mode, hipStream_t s);
+hipError_t launch_kick_drift(const Launch &L, int mode, hipStream_t s);
+hipError_t launch_kick_stats(const Launch &L, int mode, int do_kick, hipStream_t s);
+hipError_t launch_finalize_step(const Launch &L, int do_growth, hipStream_t s);
+hipError_t launch_l1_classify(const Launch &L, int mode, int init, hipStream_t s);
+hipError_t launch_finalize_l1(const Launch &L, int init, hipStream_t s);
+hipError_t launch_diag(const Launch &L, int mode, int with_pe, hipStream_t s);
+
+}  // namespace nbk

@@ -1,0 +1,119 @@
+"""CPU-side checks of libnbody: it loads, exports every entry point include/nbody.h declares,
+and validates arguments without touching a GPU."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nbody.h")
+
+
+@pytest.fixture(scope="module")
+def nb():
+    import paper_2303_12166_amd as nb
+    from paper_2303_12166_amd import build
+
+    if not os.path.exists(nb.lib_path()):
+        build.build()
+    nb.load()
+    return nb
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(nb_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for must in ("nb_scratch_bytes", "nb_create", "nb_forces", "nb_step", "nb_diagnostics",
+                 "nb_destroy", "nb_strerror"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(nb):
+    lib = ctypes.CDLL(nb.lib_path())
+    missing = [name for name in declared_functions() if not hasattr(lib, name)]
+    assert not missing
+
+
+def test_binding_covers_every_declared_symbol(nb):
+    for name in declared_functions():
+        assert callable(getattr(nb, name)), name
+
+
+def test_abi_struct_sizes_match_header(nb):
+    # nb_params: 2 int64 + 9 double + 2 int32; nb_diag: 14 double + 1 int64 + 6 int32
+    assert ctypes.sizeof(nb.NbParams) == 8 * 11 + 8
+    assert ctypes.sizeof(nb.NbBuffers) == 8 * 12
+    assert ctypes.sizeof(nb.NbDiag) == 8 * 14 + 8 + 4 * 6
+
+
+def _params(nb, **kw):
+    base = dict(n=2048, n1=1366, G=1.0, m=1.5 / 2048, dt=1e-4, D1=0.0489, D2=0.0411, q=0.5,
+                a=1.0, R2_0=0.2, growth_rate=1e-4, growth_on=1, mode=nb.NB_FP32_KAHAN)
+    base.update(kw)
+    return nb.NbParams(**base)
+
+
+def test_scratch_bytes_and_tile_config(nb):
+    small = nb.nb_scratch_bytes(_params(nb))
+    big = nb.nb_scratch_bytes(_params(nb, n=262144, n1=201650))
+    assert 0 < small < big
+    cfg = nb.nb_tile_config(262144, nb.NB_FP32_KAHAN)
+    assert cfg["iblock"] == 256 * cfg["ki"]
+    assert cfg["jchunk"] % 256 == 0
+    assert cfg["nsplit"] * cfg["jchunk"] >= 262144
+    assert nb.nb_tile_config(262144, nb.NB_FP32_PLAIN)["nsplit"] == 1
+
+
+def test_tile_override(nb):
+    before = nb.nb_tile_config(100000, nb.NB_FP32_KAHAN)["nsplit"]
+    nb.nb_tile_override(99000, 101000, 3)
+    assert nb.nb_tile_config(100000, nb.NB_FP32_KAHAN)["nsplit"] == 3
+    nb.nb_tile_override(99000, 101000, 0)
+    assert nb.nb_tile_config(100000, nb.NB_FP32_KAHAN)["nsplit"] == before
+
+
+@pytest.mark.parametrize("bad", [dict(n=-1), dict(n1=3000), dict(mode=7), dict(D1=0.0),
+                                 dict(m=float("nan")), dict(q=-0.5), dict(growth_rate=-1.0),
+                                 dict(n=1 << 31, n1=0)])
+def test_invalid_params_rejected(nb, bad):
+    with pytest.raises(nb.NbError) as e:
+        nb.nb_scratch_bytes(_params(nb, **bad))
+    assert e.value.status == nb.NB_E_INVAL
+
+
+def test_create_rejects_null_buffers_without_gpu_calls(nb):
+    with pytest.raises(nb.NbError) as e:
+        nb.nb_create(_params(nb), nb.NbBuffers())
+    assert e.value.status == nb.NB_E_INVAL
+
+
+def test_create_rejects_small_scratch(nb):
+    b = nb.NbBuffers(*([256] * 11), 16)  # aligned fake addresses, never dereferenced
+    with pytest.raises(nb.NbError) as e:
+        nb.nb_create(_params(nb), b)
+    assert e.value.status == nb.NB_E_NOMEM
+
+
+def test_step_rejects_bad_arguments(nb):
+    lib = nb.load()
+    assert lib.nb_step(None, 1, 1, None) == nb.NB_E_INVAL
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.nb_step(arr, 1, 1, None) == nb.NB_E_INVAL
+    assert lib.nb_step(arr, 0, 1, None) == nb.NB_E_INVAL
+
+
+def test_strerror_and_version(nb):
+    assert nb.nb_strerror(nb.NB_E_NOMEM).startswith("workspace")
+    assert nb.nb_strerror(12345) == "unknown status"
+    assert nb.nb_version() >= 1
+
+
+def test_timing_without_launches(nb):
+    nb.nb_timing_reset()
+    assert nb.nb_timing_read() == (0.0, 0)

@@ -1,0 +1,165 @@
+"""GPU parity of the leap-frog step, donor growth, L1 count and FP64 diagnostics.
+
+Trajectories: 100 kick-drift-kick steps at N=2048 against the FP64 oracle from the same
+FP32-rounded start (positions within 1e-5 a, velocities within 1e-4 max|v|). Donor diameters
+are FP64 on both sides with the same operations, so they must agree bitwise. L1 counts are
+integers decided in FP64 on both sides from identical inputs (the GPU's FP32 state), so they
+must agree exactly.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import print_case, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_run(ic, dt=1e-4, growth_on=True, R2_0=None):
+    p, v = ic.f32_as_f64()
+    return oracle.Run(p, v, ic.n1, ic.G, ic.m, dt, ic.D1, ic.D2, ic.q, a=ic.a,
+                      R2_0=ic.R2 if R2_0 is None else R2_0, growth_on=growth_on)
+
+
+@pytest.mark.parametrize("mode,xtol,vtol", [("kahan", 1e-5, 1e-4), ("plain", 1e-5, 1e-4),
+                                            ("fp64", 1e-11, 1e-10)])
+def test_c1_trajectory_100_steps(mode, xtol, vtol):
+    nb = require_gpu()
+    ic = synth.make_binary(2048, 0.5, seed=0)
+    print_case("c1 trajectory", mode)
+    s = nb.System.from_ic(ic, mode=mode)
+    s.step(100)
+    xg, vg = s.positions(), s.velocities()
+    dg = s.diagnostics()
+    s.close()
+    run = _oracle_run(ic)
+    run.advance(100)
+    dx = np.abs(xg - run.pos).max()
+    dv = np.abs(vg - run.vel).max()
+    vmax = np.abs(run.vel).max()
+    print("c1", mode, "max |dx|", dx, "max |dv|/max|v|", dv / vmax)
+    assert dx <= xtol * ic.a
+    assert dv <= vtol * vmax
+    assert dg["step"] == 100
+    assert dg["D2"] == run.D2  # bitwise: same FP64 operations on both sides
+
+
+def test_growth_stops_on_the_same_step_as_the_oracle():
+    nb = require_gpu()
+    ic = synth.make_binary(3000, 0.5, seed=4)
+    rl = oracle.roche_lobe(0.5)
+    R2_0 = rl * (1 - 7e-4)  # lobe reached after a handful of growth steps
+    nstar = math.ceil(math.log(rl / R2_0) / math.log(1 + 1e-4))
+    p, v = ic.f32()
+    s = nb.System(p, v, ic.n1, G=ic.G, m=ic.m, dt=1e-4, D1=ic.D1, D2=ic.D2, q=0.5, R2_0=R2_0)
+    run = _oracle_run(ic, R2_0=R2_0)
+    _, d2_log = run.advance(nstar + 4)
+    for k in range(nstar + 4):
+        s.step(1)
+        d = s.diagnostics()
+        assert d["D2"] == d2_log[k], k
+        assert d["growth_stopped"] == (k >= nstar)
+    s.close()
+
+
+def test_l1_counts_exact_on_identical_state():
+    """Donor overflowing its lobe (R2 = 0.45): many donor elements sit past L1."""
+    nb = require_gpu()
+    ic = synth.make_binary(6000, 0.5, seed=5, R2=0.45)
+    s = nb.System.from_ic(ic, mode="kahan")
+    # initial sides come from the initial positions
+    pos = s.positions().astype(np.float64)
+    n0 = oracle.l1_count(pos, ic.n1, ic.q)[0]
+    assert n0 > 0
+    assert s.diagnostics()["n_past_L1"] == n0
+    assert np.array_equal(s.sides()[ic.n1:], _past_flags(pos, ic)[ic.n1:])
+    for k in range(12):
+        s.step(5)
+        pos = s.positions().astype(np.float64)
+        assert s.diagnostics()["n_past_L1"] == oracle.l1_count(pos, ic.n1, ic.q)[0], k
+        assert np.array_equal(s.sides()[ic.n1:], _past_flags(pos, ic)[ic.n1:]), k
+    s.close()
+
+
+def _past_flags(pos, ic):
+    side = np.zeros(ic.n, dtype=np.int8)
+    oracle.l1_count(pos, ic.n1, ic.q, side, init=True)
+    return side
+
+
+def test_l1_crossing_counts_step_by_step():
+    """Rigid rotation alone moves nothing across the co-rotating L1 plane: random velocity
+    kicks (seeded) make donor elements cross in both directions."""
+    nb = require_gpu()
+    ic = synth.make_binary(6000, 0.5, seed=6, R2=0.45)
+    p, v = ic.f32()
+    rng = np.random.default_rng(60)
+    v = (v + rng.normal(0.0, 3.0, size=v.shape)).astype(np.float32)
+    s = nb.System(p, v, ic.n1, G=ic.G, m=ic.m, dt=1e-4, D1=ic.D1, D2=ic.D2, q=ic.q, R2_0=ic.R2)
+    side = np.zeros(ic.n, dtype=np.int8)
+    oracle.l1_count(s.positions().astype(np.float64), ic.n1, ic.q, side, init=True)
+    fwd = bwd = 0
+    for k in range(40):
+        s.step(1)
+        pos = s.positions().astype(np.float64)
+        expect = oracle.l1_count(pos, ic.n1, ic.q, side)
+        d = s.diagnostics()
+        assert (d["n_past_L1"], d["cross_fwd"], d["cross_bwd"]) == expect, k
+        fwd += expect[1]
+        bwd += expect[2]
+    log = s.l1_log(40)
+    s.close()
+    print("L1 crossings over 40 steps: forward", fwd, "backward", bwd)
+    assert fwd > 0 and bwd > 0
+    assert log.shape == (40, 4)
+    assert list(log[:, 0]) == list(range(1, 41))
+
+
+def test_diagnostics_match_oracle_on_identical_state():
+    nb = require_gpu()
+    for mode in ("kahan", "fp64"):
+        ic = synth.make_binary(4096, 0.6, seed=8)
+        print_case("diagnostics", mode)
+        s = nb.System.from_ic(ic, mode=mode)
+        s.step(10)
+        d = s.diagnostics(with_pe=True)
+        pos, vel = s.positions().astype(np.float64), s.velocities().astype(np.float64)
+        s.close()
+        ref = oracle.diag(pos, vel, ic.n1, ic.G, ic.m, ic.D1, d["D2"])
+        for key in ("KE", "PE", "E"):
+            assert d[key] == pytest.approx(ref[key], rel=1e-12), key
+        for key in ("com", "P", "L"):
+            scale = {"com": 1.0, "P": ic.m * np.abs(vel).sum(), "L": np.abs(ref["L"]).max()}[key]
+            assert np.abs(d[key] - ref[key]).max() <= 1e-12 * scale, key
+
+
+def test_momentum_and_energy_drift_fp32():
+    nb = require_gpu()
+    ic = synth.make_binary(8192, 0.5, seed=10)
+    s = nb.System.from_ic(ic, mode="kahan", growth_on=False)
+    d0 = s.diagnostics(with_pe=True)
+    s.step(200)
+    d1 = s.diagnostics(with_pe=True)
+    vel = s.velocities()
+    s.close()
+    dP = np.linalg.norm(d1["P"] - d0["P"]) / (ic.m * np.linalg.norm(vel, axis=1).sum())
+    dE = abs(d1["E"] - d0["E"]) / abs(d0["E"])
+    print("200 steps: dP", dP, "dE", dE)
+    assert dP < 1e-5
+    assert dE < 1e-4
+
+
+def test_nonfinite_state_is_flagged():
+    nb = require_gpu()
+    ic = synth.make_binary(3000, 0.5, seed=12)
+    s = nb.System.from_ic(ic, mode="kahan")
+    s.x[17] = float("nan")
+    s.step(1)
+    d = s.diagnostics()
+    s.close()
+    assert d["status"] == nb.NB_E_NONFINITE
+    assert d["nonfinite"] > 0
