@@ -31,7 +31,6 @@ METRIC = "pair interactions/s + % FP32 VALU peak at N=256K; served sims/s, p50/p
 FLOPS_PER_INTERACTION = 20
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 (packed FP32) x 2 (FMA) x 2.4 GHz
 PEAK_FP32_TFLOPS = 157.3
-PEAK_FP32_UNPACKED_TFLOPS = PEAK_FP32_TFLOPS / 2
 PEAK_FP64_TFLOPS = 78.6
 
 WORKLOADS = {
@@ -40,7 +39,7 @@ WORKLOADS = {
     "c4": dict(n=131072, q=0.8, mode="kahan", steps=200, warmup=5),
 }
 
-KERNEL_NAMES = {"kahan": "k_force_f32<2,true>", "plain": "k_force_f32<2,false>",
+KERNEL_NAMES = {"kahan": "k_force_f32<1,true>", "plain": "k_force_f32<1,false>",
                 "fp64": "k_force_f64"}
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "force_counters.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2303_12166_amd", "csrc", "nb_kernels.hip")
@@ -111,6 +110,53 @@ def cpu_baseline(ic, target_seconds: float):
     }, rows, ref
 
 
+def copy_calibration() -> int:
+    import torch
+
+    n = 1 << 28  # 2^28 floats = 1 GiB
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "repeats": 3}))
+    return 0
+
+
+def serving(scale: str) -> dict:
+    """Continuous batching vs one-at-a-time plain solves on one Poisson request trace."""
+    import synth
+    from paper_2303_12166_amd import serve
+
+    if scale == "full":
+        trace = synth.make_trace()  # 256 requests, 20/s, N 4096..131072, q 0.1..1, 500 steps
+        desc = "256 requests, Poisson 20/s, N log-uniform 4096..131072 (x64), q U[0.1,1], 500 steps"
+    else:
+        trace = synth.make_trace(count=48, n_max=32768, steps=100)
+        desc = "48 requests, Poisson 20/s, N log-uniform 4096..32768 (x64), q U[0.1,1], 100 steps"
+    budget = 64 << 30
+    server = serve.BatchServer(budget_bytes=budget, round_steps=10)
+    t0 = time.perf_counter()
+    batched = server.run(trace, log=log if scale == "full" else None)
+    log("batched run %.1f s (%d rounds, %d graphs)" % (time.perf_counter() - t0, server.rounds,
+                                                      server.graphs_built))
+    t0 = time.perf_counter()
+    seq = serve.run_sequential(trace)
+    log("sequential run %.1f s" % (time.perf_counter() - t0))
+    sb, ss = serve.summarize(batched), serve.summarize(seq)
+    same = all(a.digest == b.digest for a, b in zip(batched, seq))
+    return {
+        "trace": desc,
+        "budget_bytes": budget,
+        "round_steps": server.round_steps,
+        "batched": sb,
+        "sequential": ss,
+        "sims_per_s_speedup": sb["sims_per_s"] / ss["sims_per_s"],
+        "results_identical": same,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,7 +166,29 @@ def main() -> int:
     ap.add_argument("--mode", choices=["kahan", "plain", "fp64"], default=None)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--serve", choices=["none", "small", "full"], default="small",
+                    help="serving measurement: 'small' adds a 48-request trace to the main line; "
+                         "'full' runs only the 256-request trace (N 4096..131072, 500 steps)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (three times), the reference "
+                         "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes")
     args = ap.parse_args()
+    if args.copy_calibration:
+        return copy_calibration()
+    if args.serve == "full":
+        import torch
+
+        import paper_2303_12166_amd as nb
+
+        nb.load()
+        torch.cuda.set_device(0)
+        res = serving("full")
+        print(json.dumps({
+            "metric": METRIC, "value": res["batched"]["sims_per_s"], "unit": "sims/s",
+            "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic", "config": {"workload": "serving: " + res["trace"]},
+            "serving": res}), flush=True)
+        return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -150,7 +218,7 @@ def main() -> int:
     ic = synth.make_binary(n, q, seed=0)
     s = nb.System.from_ic(ic, mode=mode, dt=1e-4)
     a0 = s.accelerations()
-    cfg = nb.nb_tile_config(n, nb.MODES[mode])
+    cfg = nb.nb_tile_config(n, ic.n1, nb.MODES[mode])
     log("tile config", cfg)
 
     s.step(warmup)
@@ -188,8 +256,6 @@ def main() -> int:
         "flops_per_launch": FLOPS_PER_INTERACTION * inter,
         "kernel_interactions_per_s": inter / avg_s if avg_s > 0 else 0.0,
     }
-    if mode != "fp64":
-        roofline["frac_of_unpacked_fp32_peak"] = round(achieved / PEAK_FP32_UNPACKED_TFLOPS, 4)
 
     out = {
         "metric": METRIC,
@@ -228,6 +294,8 @@ def main() -> int:
                                     "metric": "max_i |a_gpu-a_oracle| / max_k |a_oracle|"}
     else:
         out["cpu_baseline"] = None
+    if args.serve == "small":
+        out["serving"] = serving("small")
     print(json.dumps(out), flush=True)
     return 0
 

@@ -53,6 +53,7 @@ extern "C" {
 #define NB_FP64 2       /* FP64 throughout (reference mode) */
 
 typedef struct nb_system nb_system; /* opaque, host-side, owned by the library */
+typedef struct nb_graph nb_graph;   /* opaque: a captured multi-step launch sequence */
 
 /* Physical and numerical parameters of one two-star system. */
 typedef struct {
@@ -121,6 +122,21 @@ int nb_forces(nb_system *s, void *stream);
  * systems must share one mode and must be distinct. Asynchronous on `stream`. */
 int nb_step(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *stream);
 
+/* Captures n_steps steps of the listed systems (exactly the work nb_step would queue for them)
+ * into a HIP graph with its own copy of the segment table, for replay with nb_graph_launch. The
+ * capture runs on a private stream after `stream` has been synchronised; nothing executes. The
+ * graph refers to the systems' buffers: it must be destroyed before any of them is. Force-kernel
+ * timing (nb_timing_*) does not cover graph replays. */
+int nb_graph_create(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *stream,
+                    nb_graph **out);
+
+/* Queues one replay (n_steps steps of every system in the graph) on `stream`. Replays and
+ * nb_step calls on the same systems must be ordered on one stream. */
+int nb_graph_launch(nb_graph *g, void *stream);
+
+/* Frees the graph. No replay of it may still be queued (synchronise its stream first). */
+void nb_graph_destroy(nb_graph *g);
+
 /* FP64 diagnostics: centre of mass, momentum, angular momentum, kinetic energy, and with
  * with_pe != 0 the potential energy sum_{i<j} U(r_ij) (U continuous with dU/dr = f; O(n^2)).
  * Synchronises `stream` and fills *out. Returns NB_E_NONFINITE (after filling *out) if the last
@@ -140,10 +156,13 @@ int nb_timing_enable(int32_t on);
 int nb_timing_read(double *total_ms, int64_t *launches);
 int nb_timing_reset(void);
 
-/* Tile configuration chosen for a system of n elements in a mode: elements per lane (ki), j
- * chunks per i-block (nsplit), i-block size and chunk length. Depends only on (n, mode). */
-int nb_tile_config(int64_t n, int32_t mode, int32_t *ki, int32_t *nsplit, int32_t *iblock,
-                   int32_t *jchunk);
+/* Work split chosen for a system of n elements (n1 in star 1) in a mode: i elements per lane
+ * (ki), j chunks per i-block (nsplit), i-block size and chunk length (in sorted slots). The
+ * force kernels work on a copy of the positions sorted per star (Morton order of the initial
+ * positions, each star padded to a multiple of 256 slots); results are returned in element
+ * order. Depends only on (n, n1, mode) and the overrides below. Any output pointer may be NULL. */
+int nb_tile_config(int64_t n, int64_t n1, int32_t mode, int32_t *ki, int32_t *nsplit,
+                   int32_t *iblock, int32_t *jchunk);
 
 /* Overrides the split choice for systems created afterwards whose n lies in [n_lo, n_hi]
  * (nsplit = 0 restores the built-in rule). Used by the autotuner. */

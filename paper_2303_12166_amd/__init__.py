@@ -167,15 +167,32 @@ def nb_timing_reset() -> None:
     _check(load().nb_timing_reset(), "nb_timing_reset")
 
 
-def nb_tile_config(n: int, mode: int) -> dict:
+def nb_tile_config(n: int, n1: int, mode: int) -> dict:
     v = [ctypes.c_int32(0) for _ in range(4)]
-    _check(load().nb_tile_config(int(n), int(mode), *[ctypes.byref(x) for x in v]),
+    _check(load().nb_tile_config(int(n), int(n1), int(mode), *[ctypes.byref(x) for x in v]),
            "nb_tile_config")
     return dict(zip(("ki", "nsplit", "iblock", "jchunk"), (int(x.value) for x in v)))
 
 
 def nb_tile_override(n_lo: int, n_hi: int, nsplit: int) -> None:
     _check(load().nb_tile_override(int(n_lo), int(n_hi), int(nsplit)), "nb_tile_override")
+
+
+def nb_graph_create(handles, n_steps: int, stream=None) -> ctypes.c_void_p:
+    arr = (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h
+                                             for h in handles])
+    g = ctypes.c_void_p(None)
+    _check(load().nb_graph_create(arr, len(handles), int(n_steps), _stream(stream),
+                                  ctypes.byref(g)), "nb_graph_create")
+    return g
+
+
+def nb_graph_launch(graph: ctypes.c_void_p, stream=None) -> None:
+    _check(load().nb_graph_launch(graph, _stream(stream)), "nb_graph_launch")
+
+
+def nb_graph_destroy(graph: ctypes.c_void_p) -> None:
+    load().nb_graph_destroy(graph)
 
 
 def nb_destroy(handle: ctypes.c_void_p) -> None:

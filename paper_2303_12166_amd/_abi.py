@@ -34,6 +34,9 @@ EXPORTED = (
     "nb_timing_reset",
     "nb_tile_config",
     "nb_tile_override",
+    "nb_graph_create",
+    "nb_graph_launch",
+    "nb_graph_destroy",
     "nb_destroy",
     "nb_strerror",
     "nb_version",
@@ -101,8 +104,12 @@ def declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.nb_timing_enable.argtypes = [_i32]
     lib.nb_timing_read.argtypes = [P(ctypes.c_double), P(_i64)]
     lib.nb_timing_reset.argtypes = []
-    lib.nb_tile_config.argtypes = [_i64, _i32, P(_i32), P(_i32), P(_i32), P(_i32)]
+    lib.nb_tile_config.argtypes = [_i64, _i64, _i32, P(_i32), P(_i32), P(_i32), P(_i32)]
     lib.nb_tile_override.argtypes = [_i64, _i64, _i32]
+    lib.nb_graph_create.argtypes = [P(_vp), _i32, _i32, _vp, P(_vp)]
+    lib.nb_graph_launch.argtypes = [_vp, _vp]
+    lib.nb_graph_destroy.argtypes = [_vp]
+    lib.nb_graph_destroy.restype = None
     lib.nb_destroy.argtypes = [_vp]
     lib.nb_destroy.restype = None
     lib.nb_strerror.argtypes = [ctypes.c_int]
@@ -110,6 +117,6 @@ def declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.nb_version.argtypes = []
     for name in EXPORTED:
         fn = getattr(lib, name)
-        if name not in ("nb_destroy", "nb_strerror"):
+        if name not in ("nb_destroy", "nb_strerror", "nb_graph_destroy"):
             fn.restype = ctypes.c_int
     return lib

@@ -7,15 +7,35 @@
 
 namespace nbk {
 
+// Compile-time tuning knobs of the FP32 force kernel (defaults are the shipped configuration).
+#ifndef NB_KI32
+#define NB_KI32 1          // i elements per lane
+#endif
+#ifndef NB_JUNROLL
+#define NB_JUNROLL 2       // groups of four j per unrolled inner-loop body
+#endif
+#ifndef NB_WAVES_PER_EU
+#define NB_WAVES_PER_EU 8  // > 0: ask the compiler for this many waves per SIMD (VGPR cap)
+#endif
+#if NB_WAVES_PER_EU > 0
+#define NB_FORCE_ATTR __attribute__((amdgpu_waves_per_eu(NB_WAVES_PER_EU)))
+#else
+#define NB_FORCE_ATTR
+#endif
+
 constexpr int BT = 256;          // threads per block, every kernel
 constexpr int TJ = 256;          // j elements staged in LDS per tile (one per thread)
-constexpr int KI32 = 2;          // i elements per lane, FP32 force kernel
+constexpr int KI32 = NB_KI32;    // i elements per lane, FP32 force kernel
 constexpr int KI64 = 1;          // i elements per lane, FP64 force kernel
 constexpr int RED_STRIDE = 32;   // doubles per O(N)-unit partial record
 constexpr int RED_STEP = 0;      // record slots [0, 16): per-step sums (COMs, flags, L1 counts)
 constexpr int RED_DIAG = 16;     // record slots [16, 32): diagnostics sums
 constexpr int L1_LOG_CAP = 4096; // rows of the per-step L1 log
-constexpr float SENTINEL_F32 = 1.0e18f;  // position of padding j elements (contributes exactly 0)
+// Position of padding slots in the sorted layout. A padding element at 1e18 (FP32) or 1e150
+// (FP64) gives w^3 below the type's smallest subnormal, so its contribution is exactly 0.
+constexpr float SENTINEL_F32 = 1.0e18f;
+constexpr double SENTINEL_F64 = 1.0e150;
+constexpr float FAR_MARGIN = 2.0e-5f;  // relative margin on D^2 for the far-tile test
 
 // Pair classes: 0 = star 1 with star 1, 1 = across the stars, 2 = star 2 with star 2.
 
@@ -30,6 +50,7 @@ struct alignas(16) DevState {
     double com1[3], com2[3], e[3], xi_cut;
     // FP32 copies used by the FP32 kernels
     float c1f[3], c2f[3];
+    float far2f[3];          // (1 + FAR_MARGIN) D^2 per pair class
     float gm_f, h_f, dt_f, pad_f;
     int64_t step;
     int32_t growth_on, growth_stopped;
@@ -42,11 +63,20 @@ struct DiagOut {
 };
 
 // One entry of a launch's segment table.
+//
+// The force kernels work on a sorted copy of the positions: each star's elements in Morton
+// order of their initial positions, star 1 in slots [0, n1), star 2 from slot p1 =
+// roundup(n1, TJ), both padded with sentinels to a multiple of TJ (npad slots in all, nalloc
+// allocated). Every j tile then lies inside one star, and each tile's bounding box lets the
+// kernel skip the contact test for tiles that are provably farther than D.
 struct SysDesc {
     void *x, *y, *z, *vx, *vy, *vz, *ax, *ay, *az;
     int8_t *side;
     DevState *st;
-    void *part;         // j-split partial sums, nsplit * 3 * n values (nsplit > 1 only)
+    void *xs, *ys, *zs;   // sorted positions, nalloc slots
+    int32_t *perm;        // nalloc: element index of each sorted slot, -1 for padding
+    float *tbox;          // ntiles * 8: min xyz, pad, max xyz, pad of each j tile
+    void *part;         // j-split partial sums, nsplit * 3 * nalloc values (nsplit > 1 only)
     double *red;        // n_ounits * RED_STRIDE doubles
     double *pe_part;    // n_peunits doubles
     int32_t *l1_log;    // L1_LOG_CAP * 4 int32
@@ -57,19 +87,23 @@ struct SysDesc {
     int32_t n_units, n_ounits;  // force units (n_iblocks * nsplit) and O(N) units (ceil(n / BT))
     int32_t unit_begin, ounit_begin;  // prefix offsets in the launch's segment table
     int32_t n_peunits, pad;
+    int32_t npad, p1, nalloc, ntiles;  // sorted layout (see above)
+    int32_t tunit_begin, pad2;         // prefix offset of this system's tiles in the launch
 };
 
 // Kernel argument describing one launch over a segment table.
 struct Launch {
     const SysDesc *sys;
     int32_t n_sys;
-    int32_t total_units;
-    int32_t total_ounits;
-    int32_t pad;
+    int32_t total_units;   // force units: (i-block, j chunk) pairs
+    int32_t total_ounits;  // O(N) units: 256 elements in element order
+    int32_t total_tunits;  // tiles: 256 slots in sorted order
 };
 
 // Host-side launchers (nb_kernels.hip). All return the HIP status of the launch.
 hipError_t launch_init_state(DevState *st, const DevState &init, hipStream_t s);
+hipError_t launch_fill_sorted(void *xs, void *ys, void *zs, int nalloc, int mode, hipStream_t s);
+hipError_t launch_gather(const Launch &L, int mode, hipStream_t s);
 hipError_t launch_forces(const Launch &L, int mode, hipStream_t s);
 hipError_t launch_combine(const Launch &L, int mode, hipStream_t s);
 hipError_t launch_kick_drift(const Launch &L, int mode, hipStream_t s);

@@ -80,6 +80,95 @@ __device__ __forceinline__ void kahan_add(float &sum, float &comp, float v)
 
 __device__ __forceinline__ int pair_class(int istar, int jstar) { return istar + jstar; }
 
+// ------------------------------------------------------------------ sorted layout
+
+__device__ __forceinline__ int find_tile_sys(const Launch &L, int u)
+{
+    int lo = 0, hi = L.n_sys - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (L.sys[mid].tunit_begin <= u) {
+            lo = mid;
+        } else {
+            hi = mid - 1;
+        }
+    }
+    return lo;
+}
+
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BT) void k_fill_sorted(T *xs, T *ys, T *zs, int nalloc, T sentinel)
+{
+    const int k = blockIdx.x * BT + threadIdx.x;
+    if (k < nalloc) {
+        xs[k] = sentinel;
+        ys[k] = sentinel;
+        zs[k] = sentinel;
+    }
+}
+
+// Pulls the current positions into sorted order and records each tile's bounding box (padding
+// slots keep their sentinel and are left out of the box).
+template <typename T>
+__global__ __launch_bounds__(BT) void k_gather(Launch L)
+{
+    __shared__ float lds[6][BT / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int u = blockIdx.x; u < L.total_tunits; u += gridDim.x) {
+        const SysDesc &S = L.sys[find_tile_sys(L, u)];
+        const int tile = u - S.tunit_begin;
+        const int slot = tile * TJ + threadIdx.x;
+        const int idx = S.perm[slot];
+        float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+        if (idx >= 0) {
+            const T x = static_cast<const T *>(S.x)[idx];
+            const T y = static_cast<const T *>(S.y)[idx];
+            const T z = static_cast<const T *>(S.z)[idx];
+            static_cast<T *>(S.xs)[slot] = x;
+            static_cast<T *>(S.ys)[slot] = y;
+            static_cast<T *>(S.zs)[slot] = z;
+            v[0] = v[3] = (float)x;
+            v[1] = v[4] = (float)y;
+            v[2] = v[5] = (float)z;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            v[k] = wave_min(v[k]);
+            v[3 + k] = wave_max(v[3 + k]);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) lds[k][wave] = v[k];
+        }
+        __syncthreads();
+        if (threadIdx.x < 8) {
+            const int k = threadIdx.x;
+            float r = 0.0f;
+            if (k < 3 || (k >= 4 && k < 7)) {
+                const int q = k < 3 ? k : k - 1;
+                r = lds[q][0];
+                for (int w = 1; w < BT / 64; ++w) r = q < 3 ? fminf(r, lds[q][w]) : fmaxf(r, lds[q][w]);
+            }
+            S.tbox[(size_t)tile * 8 + k] = r;
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ FP32 force kernel
 
 template <int KI>
@@ -88,113 +177,156 @@ struct IState {
     float ax[KI], ay[KI], az[KI];
 };
 
+// Near tiles: the contact law s = min(w^3, c1 - c2 w) for every pair.
 template <int KI>
-__device__ __forceinline__ void interact_tile_f32(const float *__restrict__ sx,
-                                                  const float *__restrict__ sy,
-                                                  const float *__restrict__ sz, IState<KI> &I,
-                                                  const float (&c1)[KI], const float (&nc2)[KI])
+__device__ __forceinline__ void interact4_near(const float4 &X, const float4 &Y, const float4 &Z,
+                                               IState<KI> &I, float c1, float nc2)
 {
     const float eps = 1.0e-24f;
-#pragma unroll 2
-    for (int jj = 0; jj < TJ; jj += 4) {
-        const float4 X = *reinterpret_cast<const float4 *>(sx + jj);
-        const float4 Y = *reinterpret_cast<const float4 *>(sy + jj);
-        const float4 Z = *reinterpret_cast<const float4 *>(sz + jj);
-        const float xs[4] = {X.x, X.y, X.z, X.w};
-        const float ys[4] = {Y.x, Y.y, Y.z, Y.w};
-        const float zs[4] = {Z.x, Z.y, Z.z, Z.w};
+    const float xs[4] = {X.x, X.y, X.z, X.w};
+    const float ys[4] = {Y.x, Y.y, Y.z, Y.w};
+    const float zs[4] = {Z.x, Z.y, Z.z, Z.w};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 4; ++q) {
 #pragma unroll
-            for (int k = 0; k < KI; ++k) {
-                const float dx = xs[q] - I.x[k];
-                const float dy = ys[q] - I.y[k];
-                const float dz = zs[q] - I.z[k];
-                const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
-                const float w = __builtin_amdgcn_rsqf(r2);
-                const float w3 = (w * w) * w;
-                const float s = fminf(w3, fmaf(nc2[k], w, c1[k]));
-                I.ax[k] = fmaf(s, dx, I.ax[k]);
-                I.ay[k] = fmaf(s, dy, I.ay[k]);
-                I.az[k] = fmaf(s, dz, I.az[k]);
-            }
+        for (int k = 0; k < KI; ++k) {
+            const float dx = xs[q] - I.x[k];
+            const float dy = ys[q] - I.y[k];
+            const float dz = zs[q] - I.z[k];
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
+            const float w = __builtin_amdgcn_rsqf(r2);
+            const float w3 = (w * w) * w;
+            const float s = fminf(w3, fmaf(nc2, w, c1));
+            I.ax[k] = fmaf(s, dx, I.ax[k]);
+            I.ay[k] = fmaf(s, dy, I.ay[k]);
+            I.az[k] = fmaf(s, dz, I.az[k]);
         }
     }
 }
 
-// One force unit: the i-block `ib` of system S against j chunk `c`.
+// Far tiles (every pair at r >= D, proven from bounding boxes): s = w^3, the value the contact
+// law's minimum selects there.
+template <int KI>
+__device__ __forceinline__ void interact4_far(const float4 &X, const float4 &Y, const float4 &Z,
+                                              IState<KI> &I)
+{
+    const float eps = 1.0e-24f;
+    const float xs[4] = {X.x, X.y, X.z, X.w};
+    const float ys[4] = {Y.x, Y.y, Y.z, Y.w};
+    const float zs[4] = {Z.x, Z.y, Z.z, Z.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int k = 0; k < KI; ++k) {
+            const float dx = xs[q] - I.x[k];
+            const float dy = ys[q] - I.y[k];
+            const float dz = zs[q] - I.z[k];
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
+            const float w = __builtin_amdgcn_rsqf(r2);
+            const float s = (w * w) * w;
+            I.ax[k] = fmaf(s, dx, I.ax[k]);
+            I.ay[k] = fmaf(s, dy, I.ay[k]);
+            I.az[k] = fmaf(s, dz, I.az[k]);
+        }
+    }
+}
+
+__device__ __forceinline__ float4 lds4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
+
+template <int KI, bool FAR>
+__device__ __forceinline__ void interact_tile_f32(const float *__restrict__ sx,
+                                                  const float *__restrict__ sy,
+                                                  const float *__restrict__ sz, IState<KI> &I,
+                                                  float c1, float nc2)
+{
+#pragma unroll NB_JUNROLL
+    for (int jj = 0; jj < TJ; jj += 4) {
+        const float4 X = lds4(sx + jj), Y = lds4(sy + jj), Z = lds4(sz + jj);
+        if (FAR) {
+            interact4_far<KI>(X, Y, Z, I);
+        } else {
+            interact4_near<KI>(X, Y, Z, I, c1, nc2);
+        }
+    }
+}
+
+// One force unit: i-block `ib` (BT * KI sorted slots; each wave owns 64 * KI consecutive slots)
+// against j chunk `c` (a run of whole tiles).
 template <int KI, bool KAHAN>
 __device__ __forceinline__ void force_unit_f32(const SysDesc &S, int ib, int c,
                                                float (*sh)[3][TJ])
 {
-    const int tid = threadIdx.x;
-    const int n = S.n, n1 = S.n1;
-    const float *__restrict__ X = static_cast<const float *>(S.x);
-    const float *__restrict__ Y = static_cast<const float *>(S.y);
-    const float *__restrict__ Z = static_cast<const float *>(S.z);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const float *__restrict__ XS = static_cast<const float *>(S.xs);
+    const float *__restrict__ YS = static_cast<const float *>(S.ys);
+    const float *__restrict__ ZS = static_cast<const float *>(S.zs);
     const DevState *st = S.st;
 
     IState<KI> I;
-    float c1a[KI], nc2a[KI], c1b[KI], nc2b[KI];
-    const int i0 = ib * (BT * KI);
+    const int base = ib * (BT * KI) + wave * (64 * KI);
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
 #pragma unroll
     for (int k = 0; k < KI; ++k) {
-        const int i = min(i0 + k * BT + tid, n - 1);
-        I.x[k] = X[i];
-        I.y[k] = Y[i];
-        I.z[k] = Z[i];
+        const int slot = base + k * 64 + lane;
+        I.x[k] = XS[slot];
+        I.y[k] = YS[slot];
+        I.z[k] = ZS[slot];
         I.ax[k] = I.ay[k] = I.az[k] = 0.0f;
-        const int si = i >= n1 ? 1 : 0;
-        c1a[k] = st->c1f[pair_class(si, 0)];
-        nc2a[k] = -st->c2f[pair_class(si, 0)];
-        c1b[k] = st->c1f[pair_class(si, 1)];
-        nc2b[k] = -st->c2f[pair_class(si, 1)];
+        if (S.perm[slot] >= 0) {
+            lo[0] = fminf(lo[0], I.x[k]);
+            lo[1] = fminf(lo[1], I.y[k]);
+            lo[2] = fminf(lo[2], I.z[k]);
+            hi[0] = fmaxf(hi[0], I.x[k]);
+            hi[1] = fmaxf(hi[1], I.y[k]);
+            hi[2] = fmaxf(hi[2], I.z[k]);
+        }
     }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = wave_min(lo[d]);
+        hi[d] = wave_max(hi[d]);
+    }
+    // the wave's slots lie in one star (p1 is a multiple of TJ, waves own aligned 64 KI runs)
+    const int istar = base >= S.p1 ? 1 : 0;
+    const float c1a = st->c1f[istar], nc2a = -st->c2f[istar], far2a = st->far2f[istar];
+    const float c1b = st->c1f[istar + 1], nc2b = -st->c2f[istar + 1], far2b = st->far2f[istar + 1];
+
     float sumx[KI], sumy[KI], sumz[KI], cx[KI], cy[KI], cz[KI];
 #pragma unroll
     for (int k = 0; k < KI; ++k) sumx[k] = sumy[k] = sumz[k] = cx[k] = cy[k] = cz[k] = 0.0f;
 
-    // j range of this chunk, split at n1 into a star-1 and a star-2 segment
-    const int j0 = c * S.jchunk;
-    const int j1 = min(n, j0 + S.jchunk);
-    const int a0 = j0, a1 = min(j1, n1);
-    const int b0 = max(j0, n1), b1 = j1;
-    const int ta = a1 > a0 ? (a1 - a0 + TJ - 1) / TJ : 0;
-    const int tb = b1 > b0 ? (b1 - b0 + TJ - 1) / TJ : 0;
-    const int nt = ta + tb;
-
-    auto fetch = [&](int t, float &px, float &py, float &pz) {
-        int start, end;
-        if (t < ta) {
-            start = a0 + t * TJ;
-            end = a1;
-        } else {
-            start = b0 + (t - ta) * TJ;
-            end = b1;
-        }
-        const int j = start + tid;
-        if (j < end) {
-            px = X[j];
-            py = Y[j];
-            pz = Z[j];
-        } else {
-            px = py = pz = SENTINEL_F32;
-        }
-    };
-
+    // chunk c covers tiles [c ntiles / nsplit, (c + 1) ntiles / nsplit): sizes differ by <= 1
+    const int t0 = (int)(((int64_t)c * S.ntiles) / S.nsplit);
+    const int t1 = (int)(((int64_t)(c + 1) * S.ntiles) / S.nsplit);
     float px = 0.f, py = 0.f, pz = 0.f;
-    if (nt > 0) fetch(0, px, py, pz);
-    for (int t = 0; t < nt; ++t) {
-        const int buf = t & 1;
+    if (t0 < t1) {
+        px = XS[t0 * TJ + tid];
+        py = YS[t0 * TJ + tid];
+        pz = ZS[t0 * TJ + tid];
+    }
+    for (int t = t0; t < t1; ++t) {
+        const int buf = (t - t0) & 1;
         sh[buf][0][tid] = px;
         sh[buf][1][tid] = py;
         sh[buf][2][tid] = pz;
         __syncthreads();
-        if (t + 1 < nt) fetch(t + 1, px, py, pz);
-        if (t < ta) {
-            interact_tile_f32<KI>(sh[buf][0], sh[buf][1], sh[buf][2], I, c1a, nc2a);
+        if (t + 1 < t1) {
+            px = XS[(t + 1) * TJ + tid];
+            py = YS[(t + 1) * TJ + tid];
+            pz = ZS[(t + 1) * TJ + tid];
+        }
+        const bool jstar = t * TJ >= S.p1;
+        const float *bx = S.tbox + (size_t)t * 8;
+        const float gx = fmaxf(0.0f, fmaxf(bx[0] - hi[0], lo[0] - bx[4]));
+        const float gy = fmaxf(0.0f, fmaxf(bx[1] - hi[1], lo[1] - bx[5]));
+        const float gz = fmaxf(0.0f, fmaxf(bx[2] - hi[2], lo[2] - bx[6]));
+        const float gap2 = gx * gx + gy * gy + gz * gz;
+        const int far = __builtin_amdgcn_readfirstlane(gap2 >= (jstar ? far2b : far2a) ? 1 : 0);
+        if (far) {
+            interact_tile_f32<KI, true>(sh[buf][0], sh[buf][1], sh[buf][2], I, 0.f, 0.f);
         } else {
-            interact_tile_f32<KI>(sh[buf][0], sh[buf][1], sh[buf][2], I, c1b, nc2b);
+            interact_tile_f32<KI, false>(sh[buf][0], sh[buf][1], sh[buf][2], I,
+                                         jstar ? c1b : c1a, jstar ? nc2b : nc2a);
         }
         if (KAHAN) {
 #pragma unroll
@@ -211,8 +343,9 @@ __device__ __forceinline__ void force_unit_f32(const SysDesc &S, int ib, int c,
     const float gm = st->gm_f;
 #pragma unroll
     for (int k = 0; k < KI; ++k) {
-        const int i = i0 + k * BT + tid;
-        if (i >= n) continue;
+        const int slot = base + k * 64 + lane;
+        const int idx = S.perm[slot];
+        if (idx < 0) continue;
         float vx, vy, vz;
         if (KAHAN) {
             vx = sumx[k] - cx[k];
@@ -224,21 +357,22 @@ __device__ __forceinline__ void force_unit_f32(const SysDesc &S, int ib, int c,
             vz = I.az[k];
         }
         if (S.nsplit == 1) {
-            static_cast<float *>(S.ax)[i] = gm * vx;
-            static_cast<float *>(S.ay)[i] = gm * vy;
-            static_cast<float *>(S.az)[i] = gm * vz;
+            static_cast<float *>(S.ax)[idx] = gm * vx;
+            static_cast<float *>(S.ay)[idx] = gm * vy;
+            static_cast<float *>(S.az)[idx] = gm * vz;
         } else {
             float *P = static_cast<float *>(S.part);
-            const size_t base = (size_t)c * 3 * n;
-            P[base + i] = vx;
-            P[base + n + i] = vy;
-            P[base + 2 * (size_t)n + i] = vz;
+            const size_t na = S.nalloc;
+            const size_t b = (size_t)c * 3 * na + slot;
+            P[b] = vx;
+            P[b + na] = vy;
+            P[b + 2 * na] = vz;
         }
     }
 }
 
 template <int KI, bool KAHAN>
-__global__ __launch_bounds__(BT) void k_force_f32(Launch L)
+__global__ __launch_bounds__(BT) NB_FORCE_ATTR void k_force_f32(Launch L)
 {
     __shared__ __attribute__((aligned(16))) float sh[2][3][TJ];
     for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
@@ -263,80 +397,61 @@ __device__ __forceinline__ double rsqrt_f64(double r2)
     return y;
 }
 
-__device__ void force_unit_f64(const SysDesc &S, int ib, int c, double (*sh)[4][TJ])
+__device__ void force_unit_f64(const SysDesc &S, int ib, int c, double (*sh)[TJ])
 {
     const int tid = threadIdx.x;
-    const int n = S.n, n1 = S.n1;
-    const double *__restrict__ X = static_cast<const double *>(S.x);
-    const double *__restrict__ Y = static_cast<const double *>(S.y);
-    const double *__restrict__ Z = static_cast<const double *>(S.z);
+    const double *__restrict__ XS = static_cast<const double *>(S.xs);
+    const double *__restrict__ YS = static_cast<const double *>(S.ys);
+    const double *__restrict__ ZS = static_cast<const double *>(S.zs);
     const DevState *st = S.st;
-    const int i = ib * BT + tid;
-    const int ic = min(i, n - 1);
-    const double xi = X[ic], yi = Y[ic], zi = Z[ic];
-    const int si = ic >= n1 ? 1 : 0;
+    const int slot = ib * BT + tid;
+    const double xi = XS[slot], yi = YS[slot], zi = ZS[slot];
+    const int istar = ib * BT >= S.p1 ? 1 : 0;
     double ax = 0.0, ay = 0.0, az = 0.0;
-
-    const int j0 = c * S.jchunk;
-    const int j1 = min(n, j0 + S.jchunk);
-    const int a0 = j0, a1 = min(j1, n1);
-    const int b0 = max(j0, n1), b1 = j1;
-    const int ta = a1 > a0 ? (a1 - a0 + TJ - 1) / TJ : 0;
-    const int tb = b1 > b0 ? (b1 - b0 + TJ - 1) / TJ : 0;
-    const int nt = ta + tb;
-    for (int t = 0; t < nt; ++t) {
-        int start, end, js;
-        if (t < ta) {
-            start = a0 + t * TJ;
-            end = a1;
-            js = 0;
-        } else {
-            start = b0 + (t - ta) * TJ;
-            end = b1;
-            js = 1;
-        }
-        const int j = start + tid;
-        const bool ok = j < end;
-        sh[0][0][tid] = ok ? X[j] : 0.0;
-        sh[0][1][tid] = ok ? Y[j] : 0.0;
-        sh[0][2][tid] = ok ? Z[j] : 0.0;
-        sh[0][3][tid] = ok ? 1.0 : 0.0;
+    const int t0 = (int)(((int64_t)c * S.ntiles) / S.nsplit);
+    const int t1 = (int)(((int64_t)(c + 1) * S.ntiles) / S.nsplit);
+    for (int t = t0; t < t1; ++t) {
+        sh[0][tid] = XS[t * TJ + tid];
+        sh[1][tid] = YS[t * TJ + tid];
+        sh[2][tid] = ZS[t * TJ + tid];
         __syncthreads();
-        const int cls = pair_class(si, js);
+        const int cls = pair_class(istar, t * TJ >= S.p1 ? 1 : 0);
         const double c1 = st->c1d[cls], c2 = st->c2d[cls];
         for (int jj = 0; jj < TJ; ++jj) {
-            const double dx = sh[0][0][jj] - xi;
-            const double dy = sh[0][1][jj] - yi;
-            const double dz = sh[0][2][jj] - zi;
+            const double dx = sh[0][jj] - xi;
+            const double dy = sh[1][jj] - yi;
+            const double dz = sh[2][jj] - zi;
             const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
             const double w = r2 > 0.0 ? rsqrt_f64(r2) : 0.0;
             const double w3 = w * w * w;
-            const double s = fmin(w3, c1 - c2 * w) * sh[0][3][jj];
+            const double s = fmin(w3, c1 - c2 * w);
             ax = fma(s, dx, ax);
             ay = fma(s, dy, ay);
             az = fma(s, dz, az);
         }
         __syncthreads();
     }
-    if (i < n) {
+    const int idx = S.perm[slot];
+    if (idx >= 0) {
         if (S.nsplit == 1) {
             const double gm = st->gm_d;
-            static_cast<double *>(S.ax)[i] = gm * ax;
-            static_cast<double *>(S.ay)[i] = gm * ay;
-            static_cast<double *>(S.az)[i] = gm * az;
+            static_cast<double *>(S.ax)[idx] = gm * ax;
+            static_cast<double *>(S.ay)[idx] = gm * ay;
+            static_cast<double *>(S.az)[idx] = gm * az;
         } else {
             double *P = static_cast<double *>(S.part);
-            const size_t base = (size_t)c * 3 * n;
-            P[base + i] = ax;
-            P[base + n + i] = ay;
-            P[base + 2 * (size_t)n + i] = az;
+            const size_t na = S.nalloc;
+            const size_t b = (size_t)c * 3 * na + slot;
+            P[b] = ax;
+            P[b + na] = ay;
+            P[b + 2 * na] = az;
         }
     }
 }
 
 __global__ __launch_bounds__(BT) void k_force_f64(Launch L)
 {
-    __shared__ double sh[1][4][TJ];
+    __shared__ double sh[3][TJ];
     for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
         const int s = find_sys(L, u, false);
         const SysDesc &S = L.sys[s];
@@ -349,21 +464,24 @@ __global__ __launch_bounds__(BT) void k_force_f64(Launch L)
 
 // ------------------------------------------------------------------ j-split combine
 
+// Sums the chunk partials of each sorted slot in chunk order and scatters a = G m sum to the
+// element's own index.
 template <typename T, bool KAHAN>
 __global__ __launch_bounds__(BT) void k_combine(Launch L)
 {
-    for (int u = blockIdx.x; u < L.total_ounits; u += gridDim.x) {
-        const SysDesc &S = L.sys[find_sys(L, u, true)];
+    for (int u = blockIdx.x; u < L.total_tunits; u += gridDim.x) {
+        const SysDesc &S = L.sys[find_tile_sys(L, u)];
         if (S.nsplit == 1) continue;
-        const int i = (u - S.ounit_begin) * BT + threadIdx.x;
-        if (i >= S.n) continue;
+        const int slot = (u - S.tunit_begin) * TJ + threadIdx.x;
+        const int idx = S.perm[slot];
+        if (idx < 0) continue;
         const T *P = static_cast<const T *>(S.part);
-        const size_t n = S.n;
+        const size_t na = S.nalloc;
         T out[3];
         for (int d = 0; d < 3; ++d) {
             T sum = 0, comp = 0;
             for (int c = 0; c < S.nsplit; ++c) {
-                const T v = P[(size_t)c * 3 * n + d * n + i];
+                const T v = P[(size_t)c * 3 * na + d * na + slot];
                 if (KAHAN) {
                     const T y = v - comp;
                     const T t = sum + y;
@@ -381,9 +499,9 @@ __global__ __launch_bounds__(BT) void k_combine(Launch L)
         } else {
             gm = S.st->gm_d;
         }
-        static_cast<T *>(S.ax)[i] = gm * out[0];
-        static_cast<T *>(S.ay)[i] = gm * out[1];
-        static_cast<T *>(S.az)[i] = gm * out[2];
+        static_cast<T *>(S.ax)[idx] = gm * out[0];
+        static_cast<T *>(S.ay)[idx] = gm * out[1];
+        static_cast<T *>(S.az)[idx] = gm * out[2];
     }
 }
 
@@ -509,6 +627,7 @@ __global__ __launch_bounds__(BT) void k_finalize_step(Launch L, int do_growth)
                         st->c2d[k] = 10.0 / (D * D);
                         st->c1f[k] = (float)st->c1d[k];
                         st->c2f[k] = (float)st->c2d[k];
+                        st->far2f[k] = (float)(D * D * (1.0 + (double)FAR_MARGIN));
                     }
                 } else {
                     st->growth_stopped = 1;
@@ -715,6 +834,34 @@ hipError_t launch_init_state(DevState *st, const DevState &init, hipStream_t s)
     return hipGetLastError();
 }
 
+hipError_t launch_fill_sorted(void *xs, void *ys, void *zs, int nalloc, int mode, hipStream_t s)
+{
+    if (nalloc <= 0) return hipSuccess;
+    const dim3 g((nalloc + BT - 1) / BT), b(BT);
+    if (mode == 2) {
+        hipLaunchKernelGGL(k_fill_sorted<double>, g, b, 0, s, static_cast<double *>(xs),
+                           static_cast<double *>(ys), static_cast<double *>(zs), nalloc,
+                           SENTINEL_F64);
+    } else {
+        hipLaunchKernelGGL(k_fill_sorted<float>, g, b, 0, s, static_cast<float *>(xs),
+                           static_cast<float *>(ys), static_cast<float *>(zs), nalloc,
+                           SENTINEL_F32);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const Launch &L, int mode, hipStream_t s)
+{
+    if (L.total_tunits == 0) return hipSuccess;
+    const dim3 g(grid_for(L.total_tunits)), b(BT);
+    if (mode == 2) {
+        hipLaunchKernelGGL(k_gather<double>, g, b, 0, s, L);
+    } else {
+        hipLaunchKernelGGL(k_gather<float>, g, b, 0, s, L);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_forces(const Launch &L, int mode, hipStream_t s)
 {
     if (L.total_units == 0) return hipSuccess;
@@ -731,8 +878,8 @@ hipError_t launch_forces(const Launch &L, int mode, hipStream_t s)
 
 hipError_t launch_combine(const Launch &L, int mode, hipStream_t s)
 {
-    if (L.total_ounits == 0) return hipSuccess;
-    const dim3 g(grid_for(L.total_ounits)), b(BT);
+    if (L.total_tunits == 0) return hipSuccess;
+    const dim3 g(grid_for(L.total_tunits)), b(BT);
     if (mode == 0) {
         hipLaunchKernelGGL((k_combine<float, false>), g, b, 0, s, L);
     } else if (mode == 1) {

@@ -44,6 +44,7 @@ double l1_from_accretor(double q)
 
 struct TileCfg {
     int ki, nsplit, iblock, jchunk, n_iblocks, n_units, n_ounits;
+    int npad, p1, nalloc, ntiles;
 };
 
 struct Override {
@@ -54,59 +55,113 @@ struct Override {
 std::mutex g_cfg_mu;
 std::vector<Override> g_overrides;
 
-TileCfg tile_config(int64_t n, int mode)
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// Sorted layout and work split of a system; a function of (n, n1, mode) and the overrides only.
+TileCfg tile_config(int64_t n, int64_t n1, int mode)
 {
     TileCfg c{};
     c.ki = mode == NB_FP64 ? KI64 : KI32;
     c.iblock = BT * c.ki;
-    c.n_iblocks = (int)((n + c.iblock - 1) / c.iblock);
+    c.p1 = (int)round_up(n1, TJ);
+    c.npad = c.p1 + (int)round_up(n - n1, TJ);
+    c.ntiles = c.npad / TJ;
+    c.nalloc = (int)round_up(std::max(c.npad, 1), c.iblock);
+    c.n_iblocks = c.npad > 0 ? c.nalloc / c.iblock : 0;
     c.n_ounits = (int)((n + BT - 1) / BT);
     int ns = 1;
-    if (mode != NB_FP32_PLAIN && n > 0) {
-        // aim at >= 2048 work units (8 blocks per CU on 256 CUs) with chunks of >= 2048 j
-        const int want = (2048 + c.n_iblocks - 1) / c.n_iblocks;
-        const int most = (int)std::max<int64_t>(1, n / 2048);
-        ns = std::max(1, std::min(want, most));
+    if (mode != NB_FP32_PLAIN && c.ntiles > 0) {
+        // built-in rule: about 65536 work units, chunks of 2..16 tiles
+        const int64_t per = (int64_t)c.ntiles * c.n_iblocks / 65536;
+        const int tpc = (int)std::min<int64_t>(16, std::max<int64_t>(2, per));
+        ns = std::max(1, (c.ntiles + tpc / 2) / tpc);
         std::lock_guard<std::mutex> g(g_cfg_mu);
         for (const Override &o : g_overrides) {
-            if (n >= o.lo && n <= o.hi) ns = std::max(1, o.nsplit);
+            if (n >= o.lo && n <= o.hi) ns = o.nsplit;
         }
     }
-    int64_t chunk = n > 0 ? (n + ns - 1) / ns : TJ;
-    chunk = (chunk + TJ - 1) / TJ * TJ;
-    c.jchunk = (int)chunk;
-    c.nsplit = n > 0 ? (int)((n + chunk - 1) / chunk) : 1;
+    // chunk c covers tiles [c ntiles / nsplit, (c + 1) ntiles / nsplit)
+    c.nsplit = c.ntiles > 0 ? std::max(1, std::min(ns, c.ntiles)) : 1;
+    c.jchunk = c.ntiles > 0 ? (c.ntiles + c.nsplit - 1) / c.nsplit * TJ : TJ;
     c.n_units = c.n_iblocks * c.nsplit;
     return c;
 }
 
 struct Layout {
-    size_t state, desc, diag, red, pe, log, part, total;
+    size_t state, desc, diag, red, pe, log, xs, ys, zs, perm, tbox, part, total;
 };
 
-Layout layout_for(int64_t n, int mode, const TileCfg &c)
+Layout layout_for(int mode, const TileCfg &c)
 {
     Layout L{};
+    const size_t elem = mode == NB_FP64 ? sizeof(double) : sizeof(float);
     size_t off = 0;
-    L.state = off;
-    off = align_up(off + sizeof(DevState), ALIGN);
-    L.desc = off;
-    off = align_up(off + sizeof(SysDesc), ALIGN);
-    L.diag = off;
-    off = align_up(off + sizeof(DiagOut), ALIGN);
-    L.red = off;
-    off = align_up(off + (size_t)std::max(c.n_ounits, 1) * RED_STRIDE * sizeof(double), ALIGN);
-    L.pe = off;
-    off = align_up(off + (size_t)std::max(c.n_ounits, 1) * sizeof(double), ALIGN);
-    L.log = off;
-    off = align_up(off + (size_t)L1_LOG_CAP * 4 * sizeof(int32_t), ALIGN);
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes, ALIGN);
+        return at;
+    };
+    L.state = take(sizeof(DevState));
+    L.desc = take(sizeof(SysDesc));
+    L.diag = take(sizeof(DiagOut));
+    L.red = take((size_t)std::max(c.n_ounits, 1) * RED_STRIDE * sizeof(double));
+    L.pe = take((size_t)std::max(c.n_ounits, 1) * sizeof(double));
+    L.log = take((size_t)L1_LOG_CAP * 4 * sizeof(int32_t));
+    L.xs = take((size_t)c.nalloc * elem);
+    L.ys = take((size_t)c.nalloc * elem);
+    L.zs = take((size_t)c.nalloc * elem);
+    L.perm = take((size_t)c.nalloc * sizeof(int32_t));
+    L.tbox = take((size_t)std::max(c.ntiles, 1) * 8 * sizeof(float));
     L.part = off;
-    if (c.nsplit > 1) {
-        const size_t elem = mode == NB_FP64 ? sizeof(double) : sizeof(float);
-        off = align_up(off + (size_t)c.nsplit * 3 * (size_t)n * elem, ALIGN);
-    }
+    if (c.nsplit > 1) take((size_t)c.nsplit * 3 * (size_t)c.nalloc * elem);
     L.total = off;
     return L;
+}
+
+// Morton order of each star's initial positions (10 bits per axis inside the star's bounding
+// box, ties by index): consecutive sorted slots are close in space, so tiles have small boxes.
+uint32_t spread10(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+template <typename T>
+void morton_order(const T *x, const T *y, const T *z, int64_t b, int64_t e,
+                  std::vector<int32_t> &out)
+{
+    out.clear();
+    if (e <= b) return;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t i = b; i < e; ++i) {
+        const double p[3] = {(double)x[i], (double)y[i], (double)z[i]};
+        for (int d = 0; d < 3; ++d) {
+            if (std::isfinite(p[d])) {
+                lo[d] = std::min(lo[d], p[d]);
+                hi[d] = std::max(hi[d], p[d]);
+            }
+        }
+    }
+    std::vector<std::pair<uint32_t, int32_t>> keys((size_t)(e - b));
+    for (int64_t i = b; i < e; ++i) {
+        const double p[3] = {(double)x[i], (double)y[i], (double)z[i]};
+        uint32_t q[3];
+        for (int d = 0; d < 3; ++d) {
+            const double span = hi[d] > lo[d] ? hi[d] - lo[d] : 1.0;
+            double f = std::isfinite(p[d]) ? (p[d] - lo[d]) / span : 0.0;
+            f = std::min(std::max(f, 0.0), 1.0);
+            q[d] = (uint32_t)std::min(1023.0, f * 1024.0);
+        }
+        keys[(size_t)(i - b)] = {spread10(q[0]) | (spread10(q[1]) << 1) | (spread10(q[2]) << 2),
+                                 (int32_t)i};
+    }
+    std::sort(keys.begin(), keys.end());
+    out.resize(keys.size());
+    for (size_t k = 0; k < keys.size(); ++k) out[k] = keys[k].second;
 }
 
 bool params_ok(const nb_params *p)
@@ -145,6 +200,13 @@ std::vector<BatchTable> g_batches;
 
 }  // namespace
 
+struct nb_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    SysDesc *d_table = nullptr;  // the graph's own segment table
+    int n_sys = 0, n_steps = 0;
+};
+
 struct nb_system {
     nb_params p;
     nb_buffers b;
@@ -167,11 +229,13 @@ int hip_status(hipError_t e) { return e == hipSuccess ? NB_OK : NB_E_HIP; }
         if (e_ != hipSuccess) return NB_E_HIP; \
     } while (0)
 
-int launch_force_timed(const Launch &L, int mode, hipStream_t st, bool need_combine)
+int launch_force_timed(const Launch &L, int mode, hipStream_t st, bool need_combine,
+                       bool allow_timing = true)
 {
+    NB_TRY(launch_gather(L, mode, st));
     hipEvent_t a = nullptr, b = nullptr;
     bool timed = false;
-    {
+    if (allow_timing) {
         std::lock_guard<std::mutex> g(g_timing.mu);
         timed = g_timing.on;
     }
@@ -190,11 +254,12 @@ int launch_force_timed(const Launch &L, int mode, hipStream_t st, bool need_comb
     return NB_OK;
 }
 
-int run_steps(const Launch &L, int mode, int n_steps, bool need_combine, hipStream_t st)
+int run_steps(const Launch &L, int mode, int n_steps, bool need_combine, hipStream_t st,
+              bool allow_timing = true)
 {
     for (int k = 0; k < n_steps; ++k) {
         NB_TRY(launch_kick_drift(L, mode, st));
-        int rc = launch_force_timed(L, mode, st, need_combine);
+        int rc = launch_force_timed(L, mode, st, need_combine, allow_timing);
         if (rc != NB_OK) return rc;
         NB_TRY(launch_kick_stats(L, mode, 1, st));
         NB_TRY(launch_finalize_step(L, 1, st));
@@ -211,16 +276,51 @@ Launch single_launch(const nb_system *s)
     L.n_sys = 1;
     L.total_units = s->cfg.n_units;
     L.total_ounits = s->cfg.n_ounits;
+    L.total_tunits = s->cfg.ntiles;
     return L;
 }
 
 bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
+int check_system_list(nb_system *const *sys, int32_t n_sys)
+{
+    if (!sys || n_sys < 1) return NB_E_INVAL;
+    for (int k = 0; k < n_sys; ++k) {
+        if (!sys[k]) return NB_E_INVAL;
+        if (sys[k]->p.mode != sys[0]->p.mode) return NB_E_MISMATCH;
+        for (int j = 0; j < k; ++j) {
+            if (sys[j] == sys[k]) return NB_E_INVAL;
+        }
+    }
+    return NB_OK;
+}
+
+// Segment table of several systems: each system's units follow the previous system's.
+Launch build_table(nb_system *const *sys, int32_t n_sys, std::vector<SysDesc> &table,
+                   bool &combine)
+{
+    table.resize(n_sys);
+    Launch L{};
+    combine = false;
+    for (int k = 0; k < n_sys; ++k) {
+        table[k] = sys[k]->desc;
+        table[k].unit_begin = L.total_units;
+        table[k].ounit_begin = L.total_ounits;
+        table[k].tunit_begin = L.total_tunits;
+        L.total_units += sys[k]->cfg.n_units;
+        L.total_ounits += sys[k]->cfg.n_ounits;
+        L.total_tunits += sys[k]->cfg.ntiles;
+        combine = combine || sys[k]->cfg.nsplit > 1;
+    }
+    L.n_sys = n_sys;
+    return L;
+}
+
 }  // namespace
 
 extern "C" {
 
-int nb_version(void) { return 1; }
+int nb_version(void) { return 2; }
 
 const char *nb_strerror(int status)
 {
@@ -235,12 +335,12 @@ const char *nb_strerror(int status)
     }
 }
 
-int nb_tile_config(int64_t n, int32_t mode, int32_t *ki, int32_t *nsplit, int32_t *iblock,
-                   int32_t *jchunk)
+int nb_tile_config(int64_t n, int64_t n1, int32_t mode, int32_t *ki, int32_t *nsplit,
+                   int32_t *iblock, int32_t *jchunk)
 {
-    if (n < 0 || n >= (int64_t(1) << 31)) return NB_E_INVAL;
+    if (n < 0 || n >= (int64_t(1) << 31) || n1 < 0 || n1 > n) return NB_E_INVAL;
     if (mode != NB_FP32_PLAIN && mode != NB_FP32_KAHAN && mode != NB_FP64) return NB_E_INVAL;
-    TileCfg c = tile_config(n, mode);
+    TileCfg c = tile_config(n, n1, mode);
     if (ki) *ki = c.ki;
     if (nsplit) *nsplit = c.nsplit;
     if (iblock) *iblock = c.iblock;
@@ -262,8 +362,8 @@ int nb_tile_override(int64_t n_lo, int64_t n_hi, int32_t nsplit)
 int nb_scratch_bytes(const nb_params *p, size_t *out)
 {
     if (!params_ok(p) || !out) return NB_E_INVAL;
-    TileCfg c = tile_config(p->n, p->mode);
-    *out = layout_for(p->n, p->mode, c).total;
+    TileCfg c = tile_config(p->n, p->n1, p->mode);
+    *out = layout_for(p->mode, c).total;
     return NB_OK;
 }
 
@@ -281,8 +381,8 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
         if (!b->side) return NB_E_INVAL;
     }
     if (!b->scratch || !aligned(b->scratch, ALIGN)) return NB_E_INVAL;
-    TileCfg cfg = tile_config(p->n, p->mode);
-    Layout lay = layout_for(p->n, p->mode, cfg);
+    TileCfg cfg = tile_config(p->n, p->n1, p->mode);
+    Layout lay = layout_for(p->mode, cfg);
     if (b->scratch_bytes < lay.total) return NB_E_NOMEM;
 
     nb_system *s = new (std::nothrow) nb_system();
@@ -314,6 +414,16 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
     d.side = static_cast<int8_t *>(b->side);
     d.st = s->d_state;
     d.part = cfg.nsplit > 1 ? base + lay.part : nullptr;
+    d.xs = base + lay.xs;
+    d.ys = base + lay.ys;
+    d.zs = base + lay.zs;
+    d.perm = reinterpret_cast<int32_t *>(base + lay.perm);
+    d.tbox = reinterpret_cast<float *>(base + lay.tbox);
+    d.npad = cfg.npad;
+    d.p1 = cfg.p1;
+    d.nalloc = cfg.nalloc;
+    d.ntiles = cfg.ntiles;
+    d.tunit_begin = 0;
     d.red = reinterpret_cast<double *>(base + lay.red);
     d.pe_part = reinterpret_cast<double *>(base + lay.pe);
     d.l1_log = reinterpret_cast<int32_t *>(base + lay.log);
@@ -348,6 +458,7 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
         init.c2d[k] = 10.0 / (Ds[k] * Ds[k]);
         init.c1f[k] = (float)init.c1d[k];
         init.c2f[k] = (float)init.c2d[k];
+        init.far2f[k] = (float)(Ds[k] * Ds[k] * (1.0 + (double)FAR_MARGIN));
     }
     init.gm_d = p->G * p->m;
     init.h_d = 0.5 * p->dt;
@@ -359,6 +470,36 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
     hipStream_t st = static_cast<hipStream_t>(stream);
     int rc = NB_OK;
     do {
+        // sorted layout: permutation from the initial positions (host-side Morton sort)
+        std::vector<int32_t> perm((size_t)cfg.nalloc, -1);
+        if (p->n > 0) {
+            const size_t bytes = (size_t)p->n * elem;
+            std::vector<char> hx(bytes), hy(bytes), hz(bytes);
+            if (hipMemcpyAsync(hx.data(), b->x, bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipMemcpyAsync(hy.data(), b->y, bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipMemcpyAsync(hz.data(), b->z, bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess) { rc = NB_E_HIP; break; }
+            std::vector<int32_t> o1, o2;
+            if (p->mode == NB_FP64) {
+                const double *X = (const double *)hx.data(), *Y = (const double *)hy.data(),
+                             *Z = (const double *)hz.data();
+                morton_order(X, Y, Z, 0, p->n1, o1);
+                morton_order(X, Y, Z, p->n1, p->n, o2);
+            } else {
+                const float *X = (const float *)hx.data(), *Y = (const float *)hy.data(),
+                            *Z = (const float *)hz.data();
+                morton_order(X, Y, Z, 0, p->n1, o1);
+                morton_order(X, Y, Z, p->n1, p->n, o2);
+            }
+            std::copy(o1.begin(), o1.end(), perm.begin());
+            std::copy(o2.begin(), o2.end(), perm.begin() + cfg.p1);
+        }
+        if (hipMemcpyAsync(d.perm, perm.data(), perm.size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st) != hipSuccess) { rc = NB_E_HIP; break; }
+        if (launch_fill_sorted(d.xs, d.ys, d.zs, cfg.nalloc, p->mode, st) != hipSuccess) {
+            rc = NB_E_HIP;
+            break;
+        }
         if (launch_init_state(s->d_state, init, st) != hipSuccess) { rc = NB_E_HIP; break; }
         if (hipMemcpyAsync(s->d_desc, &s->desc, sizeof(SysDesc), hipMemcpyHostToDevice, st) !=
             hipSuccess) { rc = NB_E_HIP; break; }
@@ -367,6 +508,7 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
         if (launch_finalize_step(L, 0, st) != hipSuccess) { rc = NB_E_HIP; break; }
         if (launch_l1_classify(L, p->mode, 1, st) != hipSuccess) { rc = NB_E_HIP; break; }
         if (launch_finalize_l1(L, 1, st) != hipSuccess) { rc = NB_E_HIP; break; }
+        if (launch_gather(L, p->mode, st) != hipSuccess) { rc = NB_E_HIP; break; }
         if (launch_forces(L, p->mode, st) != hipSuccess) { rc = NB_E_HIP; break; }
         if (cfg.nsplit > 1 && launch_combine(L, p->mode, st) != hipSuccess) { rc = NB_E_HIP; break; }
         if (hipStreamSynchronize(st) != hipSuccess) { rc = NB_E_HIP; break; }
@@ -388,14 +530,9 @@ int nb_forces(nb_system *s, void *stream)
 
 int nb_step(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *stream)
 {
-    if (!sys || n_sys < 1 || n_steps < 0) return NB_E_INVAL;
-    for (int k = 0; k < n_sys; ++k) {
-        if (!sys[k]) return NB_E_INVAL;
-        if (sys[k]->p.mode != sys[0]->p.mode) return NB_E_MISMATCH;
-        for (int j = 0; j < k; ++j) {
-            if (sys[j] == sys[k]) return NB_E_INVAL;
-        }
-    }
+    if (n_steps < 0) return NB_E_INVAL;
+    const int chk = check_system_list(sys, n_sys);
+    if (chk != NB_OK) return chk;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int mode = sys[0]->p.mode;
     if (n_sys == 1) {
@@ -413,17 +550,9 @@ int nb_step(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *stream)
         bt = &g_batches.back();
         bt->device = device;
     }
-    std::vector<SysDesc> table(n_sys);
-    int units = 0, ounits = 0;
+    std::vector<SysDesc> table;
     bool combine = false;
-    for (int k = 0; k < n_sys; ++k) {
-        table[k] = sys[k]->desc;
-        table[k].unit_begin = units;
-        table[k].ounit_begin = ounits;
-        units += sys[k]->cfg.n_units;
-        ounits += sys[k]->cfg.n_ounits;
-        combine = combine || sys[k]->cfg.nsplit > 1;
-    }
+    Launch L = build_table(sys, n_sys, table, combine);
     const bool same = bt->last.size() == table.size() &&
                       std::memcmp(bt->last.data(), table.data(), table.size() * sizeof(SysDesc)) == 0;
     if (!same) {
@@ -452,12 +581,82 @@ int nb_step(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *stream)
                               st));
         bt->last = table;
     }
-    Launch L{};
     L.sys = bt->d;
-    L.n_sys = n_sys;
-    L.total_units = units;
-    L.total_ounits = ounits;
     return run_steps(L, mode, n_steps, combine, st);
+}
+
+int nb_graph_create(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *stream,
+                    nb_graph **out)
+{
+    if (!out) return NB_E_INVAL;
+    *out = nullptr;
+    if (n_steps < 1) return NB_E_INVAL;
+    const int chk = check_system_list(sys, n_sys);
+    if (chk != NB_OK) return chk;
+    std::vector<SysDesc> table;
+    bool combine = false;
+    Launch L = build_table(sys, n_sys, table, combine);
+    nb_graph *g = new (std::nothrow) nb_graph();
+    if (!g) return NB_E_NOMEM;
+    g->n_sys = n_sys;
+    g->n_steps = n_steps;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipStream_t cs = nullptr;
+    int rc = NB_OK;
+    do {
+        if (hipMalloc(&g->d_table, table.size() * sizeof(SysDesc)) != hipSuccess) {
+            g->d_table = nullptr;
+            rc = NB_E_NOMEM;
+            break;
+        }
+        if (hipMemcpyAsync(g->d_table, table.data(), table.size() * sizeof(SysDesc),
+                           hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) { rc = NB_E_HIP; break; }
+        L.sys = g->d_table;
+        if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+            cs = nullptr;
+            rc = NB_E_HIP;
+            break;
+        }
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            rc = NB_E_HIP;
+            break;
+        }
+        rc = run_steps(L, sys[0]->p.mode, n_steps, combine, cs, false);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(cs, &graph);
+        g->graph = graph;
+        if (rc != NB_OK) break;
+        if (e != hipSuccess || !graph) { rc = NB_E_HIP; break; }
+        if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            g->exec = nullptr;
+            rc = NB_E_HIP;
+            break;
+        }
+    } while (0);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (rc != NB_OK) {
+        nb_graph_destroy(g);
+        return rc;
+    }
+    *out = g;
+    return NB_OK;
+}
+
+int nb_graph_launch(nb_graph *g, void *stream)
+{
+    if (!g || !g->exec) return NB_E_INVAL;
+    NB_TRY(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+    return NB_OK;
+}
+
+void nb_graph_destroy(nb_graph *g)
+{
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->d_table) (void)hipFree(g->d_table);
+    delete g;
 }
 
 int nb_diagnostics(nb_system *s, int32_t with_pe, nb_diag *out, void *stream)

@@ -1,0 +1,280 @@
+"""Continuous-batching server for two-star simulation requests.
+
+Requests (N elements, mass ratio q, seed, step count) arrive over time. The server keeps every
+admitted system's state on the GPU and advances all of them together: each round replays one
+captured HIP graph that holds K leap-frog steps of every active system (one launch per kernel per
+step over the whole segment table). Between rounds it retires finished systems, admits waiting
+requests first-come first-served while their device footprint fits the memory budget, and builds
+newly admitted systems on a second stream in a worker thread, so admission overlaps the running
+rounds. A request whose footprint exceeds the whole budget is rejected.
+
+The one-at-a-time baseline runs the same trace through the plain path: each request, in arrival
+order, is created and stepped alone to completion before the next one starts.
+
+Each system's kernels, work split and reduction orders depend on its own size only, so its result
+is bitwise the same alone and in any mix; both runs record a digest of every final state.
+"""
+
+from __future__ import annotations
+
+import collections
+import dataclasses
+import hashlib
+import queue
+import threading
+import time
+
+import numpy as np
+
+from . import (
+    MODES,
+    NB_FP64,
+    NbParams,
+    nb_graph_create,
+    nb_graph_destroy,
+    nb_graph_launch,
+    nb_scratch_bytes,
+)
+from .system import System
+
+
+@dataclasses.dataclass
+class Record:
+    rid: int
+    n: int
+    q: float
+    steps: int
+    t_arrive: float
+    t_admit: float = float("nan")
+    t_done: float = float("nan")
+    bytes: int = 0
+    status: str = "pending"
+    digest: str = ""
+
+
+def footprint_bytes(n: int, q: float, mode: str = "kahan") -> int:
+    """Device bytes one system holds: nine state arrays, the side flags and the workspace."""
+    import synth
+
+    n1, _ = synth.particle_counts(n, q)
+    m = MODES[mode]
+    p = NbParams(n=n, n1=n1, G=1.0, m=1.0, dt=1e-4, D1=1.0, D2=1.0, q=q, a=1.0, R2_0=1.0,
+                 growth_rate=1e-4, growth_on=1, mode=m)
+    elem = 8 if m == NB_FP64 else 4
+    return 9 * max(n, 1) * elem + max(n, 1) + nb_scratch_bytes(p) + 256
+
+
+def state_digest(system: System) -> str:
+    h = hashlib.sha256()
+    system.synchronize()
+    for t in (system.x, system.y, system.z, system.vx, system.vy, system.vz):
+        h.update(t[: system.n].cpu().numpy().tobytes())
+    return h.hexdigest()[:32]
+
+
+def _build(req, mode: str, dt: float, stream) -> System:
+    import synth
+
+    ic = synth.make_binary(req.n, req.q, seed=req.seed)
+    return System.from_ic(ic, mode=mode, dt=dt, stream=stream)
+
+
+def summarize(records, t0: float = 0.0) -> dict:
+    done = [r for r in records if r.status == "done"]
+    if not done:
+        return {"completed": 0}
+    lat = np.array([r.t_done - r.t_arrive for r in done])
+    span = max(r.t_done for r in done) - min(r.t_arrive for r in records)
+    inter = float(sum(float(r.n) ** 2 * r.steps for r in done))
+    return {
+        "completed": len(done),
+        "rejected": sum(r.status == "rejected" for r in records),
+        "span_s": span,
+        "sims_per_s": len(done) / span if span > 0 else float("nan"),
+        "interactions_per_s": inter / span if span > 0 else float("nan"),
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "latency_mean_s": float(lat.mean()),
+        "latency_max_s": float(lat.max()),
+    }
+
+
+class BatchServer:
+    def __init__(self, budget_bytes: int, round_steps: int = 10, max_active: int = 512,
+                 mode: str = "kahan", dt: float = 1e-4, use_graphs: bool = True,
+                 keep_digests: bool = True):
+        import torch
+
+        self.torch = torch
+        self.budget = int(budget_bytes)
+        self.round_steps = int(round_steps)
+        self.max_active = int(max_active)
+        self.mode = mode
+        self.dt = dt
+        self.use_graphs = use_graphs
+        self.keep_digests = keep_digests
+        self.compute = torch.cuda.Stream()
+        self.admit_stream = torch.cuda.Stream()
+        self.rounds = 0
+        self.graphs_built = 0
+
+    # -------------------------------------------------------------- admission worker
+
+    def _worker(self, todo: "queue.Queue", ready: "queue.Queue"):
+        while True:
+            item = todo.get()
+            if item is None:
+                return
+            req, rec = item
+            try:
+                sysm = _build(req, self.mode, self.dt, self.admit_stream)
+                sysm.use_on(self.compute)
+                ready.put((req, rec, sysm, None))
+            except Exception as e:  # reported by the main loop
+                ready.put((req, rec, None, e))
+
+    # -------------------------------------------------------------- main loop
+
+    def run(self, trace, log=None) -> list:
+        recs = {r.rid: Record(r.rid, r.n, r.q, r.steps, r.t_arrive) for r in trace}
+        pending = collections.deque(sorted(trace, key=lambda r: (r.t_arrive, r.rid)))
+        waiting = collections.deque()
+        todo, ready = queue.Queue(), queue.Queue()
+        worker = threading.Thread(target=self._worker, args=(todo, ready), daemon=True)
+        worker.start()
+        active = []  # [System, Record, remaining]
+        reserved = 0
+        in_flight = 0
+        graph, graph_key = None, None
+        t0 = time.perf_counter()
+
+        def now():
+            return time.perf_counter() - t0
+
+        try:
+            while pending or waiting or active or in_flight:
+                t = now()
+                while pending and pending[0].t_arrive <= t:
+                    req = pending.popleft()
+                    rec = recs[req.rid]
+                    rec.bytes = footprint_bytes(req.n, req.q, self.mode)
+                    if rec.bytes > self.budget:
+                        rec.status = "rejected"
+                        continue
+                    waiting.append(req)
+                while (waiting and reserved + recs[waiting[0].rid].bytes <= self.budget
+                       and len(active) + in_flight < self.max_active):
+                    req = waiting.popleft()
+                    rec = recs[req.rid]
+                    reserved += rec.bytes
+                    rec.t_admit = now()
+                    rec.status = "admitted"
+                    in_flight += 1
+                    todo.put((req, rec))
+                changed = False
+                while True:
+                    try:
+                        req, rec, sysm, err = ready.get_nowait()
+                    except queue.Empty:
+                        break
+                    in_flight -= 1
+                    if err is not None:
+                        raise err
+                    active.append([sysm, rec, req.steps])
+                    changed = True
+                if not active:
+                    # idle: wait for an arrival or a system under construction
+                    nxt = pending[0].t_arrive - now() if pending else 0.002
+                    if in_flight:
+                        try:
+                            item = ready.get(timeout=max(1e-4, min(nxt, 0.05)))
+                            ready.put(item)
+                        except queue.Empty:
+                            pass
+                    elif nxt > 0:
+                        time.sleep(min(nxt, 0.05))
+                    continue
+                k = min(self.round_steps, min(a[2] for a in active))
+                key = (tuple(id(a[0]) for a in active), k)
+                if self.use_graphs:
+                    if changed or key != graph_key:
+                        if graph is not None:
+                            nb_graph_destroy(graph)
+                        graph = nb_graph_create([a[0].handle for a in active], k, self.compute)
+                        graph_key = key
+                        self.graphs_built += 1
+                    nb_graph_launch(graph, self.compute)
+                else:
+                    from . import nb_step
+
+                    nb_step([a[0].handle for a in active], k, self.compute)
+                self.compute.synchronize()
+                self.rounds += 1
+                t = now()
+                keep = []
+                retired = False
+                for a in active:
+                    a[2] -= k
+                    if a[2] <= 0:
+                        sysm, rec = a[0], a[1]
+                        rec.t_done = t
+                        rec.status = "done"
+                        if self.keep_digests:
+                            rec.digest = state_digest(sysm)
+                        retired = True
+                    else:
+                        keep.append(a)
+                if retired:
+                    if graph is not None:
+                        nb_graph_destroy(graph)
+                        graph, graph_key = None, None
+                    for a in active:
+                        if a[2] <= 0:
+                            reserved -= a[1].bytes
+                            a[0].close()
+                    active = keep
+                    if log:
+                        log("t=%.2fs active=%d waiting=%d done=%d" % (
+                            t, len(active), len(waiting),
+                            sum(r.status == "done" for r in recs.values())))
+        finally:
+            todo.put(None)
+            worker.join(timeout=60)
+            if graph is not None:
+                self.compute.synchronize()
+                nb_graph_destroy(graph)
+            for a in active:
+                a[0].close()
+        return [recs[r.rid] for r in trace]
+
+
+def run_sequential(trace, mode: str = "kahan", dt: float = 1e-4, chunk: int = 100,
+                   keep_digests: bool = True, log=None) -> list:
+    """One system at a time, in arrival order, each stepped alone to completion (plain path)."""
+    import torch
+
+    stream = torch.cuda.Stream()
+    recs = [Record(r.rid, r.n, r.q, r.steps, r.t_arrive) for r in trace]
+    order = sorted(range(len(trace)), key=lambda i: (trace[i].t_arrive, trace[i].rid))
+    t0 = time.perf_counter()
+    for i in order:
+        req, rec = trace[i], recs[i]
+        wait = req.t_arrive - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        rec.t_admit = time.perf_counter() - t0
+        sysm = _build(req, mode, dt, stream)
+        left = req.steps
+        while left > 0:
+            k = min(chunk, left)
+            sysm.step(k)
+            left -= k
+        sysm.synchronize()
+        rec.t_done = time.perf_counter() - t0
+        rec.status = "done"
+        if keep_digests:
+            rec.digest = state_digest(sysm)
+        sysm.close()
+        if log:
+            log("seq t=%.2fs done rid=%d n=%d" % (rec.t_done, rec.rid, rec.n))
+    return recs

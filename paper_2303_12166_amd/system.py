@@ -45,17 +45,20 @@ class System:
                                mode=self.mode)
         nbytes = nb_scratch_bytes(self.params)
         k = dict(dtype=dtype, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
 
         def col(a, c):
             return torch.from_numpy(np.ascontiguousarray(a[:, c])).to(**k) if n else \
                 torch.zeros(1, **k)
 
-        self.x, self.y, self.z = col(pos, 0), col(pos, 1), col(pos, 2)
-        self.vx, self.vy, self.vz = col(vel, 0), col(vel, 1), col(vel, 2)
-        self.ax, self.ay, self.az = (torch.zeros(max(n, 1), **k) for _ in range(3))
-        self.side = torch.zeros(max(n, 1), dtype=torch.int8, device=self.device)
-        # 256-byte alignment: over-allocate and offset
-        self._scratch = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        # every upload and allocation is ordered on the system's stream
+        with torch.cuda.stream(self.stream):
+            self.x, self.y, self.z = col(pos, 0), col(pos, 1), col(pos, 2)
+            self.vx, self.vy, self.vz = col(vel, 0), col(vel, 1), col(vel, 2)
+            self.ax, self.ay, self.az = (torch.zeros(max(n, 1), **k) for _ in range(3))
+            self.side = torch.zeros(max(n, 1), dtype=torch.int8, device=self.device)
+            # 256-byte alignment: over-allocate and offset
+            self._scratch = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self._scratch.data_ptr()
         off = (-base) % 256
         self.buffers = NbBuffers(
@@ -63,7 +66,6 @@ class System:
             vx=self.vx.data_ptr(), vy=self.vy.data_ptr(), vz=self.vz.data_ptr(),
             ax=self.ax.data_ptr(), ay=self.ay.data_ptr(), az=self.az.data_ptr(),
             side=self.side.data_ptr(), scratch=base + off, scratch_bytes=nbytes)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.handle = nb_create(self.params, self.buffers, self.stream)
 
     @classmethod
@@ -93,6 +95,15 @@ class System:
 
     def synchronize(self):
         self.stream.synchronize()
+
+    def tensors(self):
+        return (self.x, self.y, self.z, self.vx, self.vy, self.vz, self.ax, self.ay, self.az,
+                self.side, self._scratch)
+
+    def use_on(self, stream):
+        """Marks the device tensors as used on another stream (for PyTorch's allocator)."""
+        for t in self.tensors():
+            t.record_stream(stream)
 
     # ------------------------------------------------------------ state read-back
 

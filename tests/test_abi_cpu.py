@@ -63,19 +63,19 @@ def test_scratch_bytes_and_tile_config(nb):
     small = nb.nb_scratch_bytes(_params(nb))
     big = nb.nb_scratch_bytes(_params(nb, n=262144, n1=201650))
     assert 0 < small < big
-    cfg = nb.nb_tile_config(262144, nb.NB_FP32_KAHAN)
+    cfg = nb.nb_tile_config(262144, 201650, nb.NB_FP32_KAHAN)
     assert cfg["iblock"] == 256 * cfg["ki"]
     assert cfg["jchunk"] % 256 == 0
     assert cfg["nsplit"] * cfg["jchunk"] >= 262144
-    assert nb.nb_tile_config(262144, nb.NB_FP32_PLAIN)["nsplit"] == 1
+    assert nb.nb_tile_config(262144, 201650, nb.NB_FP32_PLAIN)["nsplit"] == 1
 
 
 def test_tile_override(nb):
-    before = nb.nb_tile_config(100000, nb.NB_FP32_KAHAN)["nsplit"]
+    before = nb.nb_tile_config(100000, 60000, nb.NB_FP32_KAHAN)["nsplit"]
     nb.nb_tile_override(99000, 101000, 3)
-    assert nb.nb_tile_config(100000, nb.NB_FP32_KAHAN)["nsplit"] == 3
+    assert nb.nb_tile_config(100000, 60000, nb.NB_FP32_KAHAN)["nsplit"] == 3
     nb.nb_tile_override(99000, 101000, 0)
-    assert nb.nb_tile_config(100000, nb.NB_FP32_KAHAN)["nsplit"] == before
+    assert nb.nb_tile_config(100000, 60000, nb.NB_FP32_KAHAN)["nsplit"] == before
 
 
 @pytest.mark.parametrize("bad", [dict(n=-1), dict(n1=3000), dict(mode=7), dict(D1=0.0),

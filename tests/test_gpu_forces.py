@@ -141,7 +141,7 @@ def test_j_split_choices_agree(nsplit):
     ic = synth.make_binary(n, 0.6, seed=2)
     nb.nb_tile_override(n, n, nsplit)
     try:
-        cfg = nb.nb_tile_config(n, nb.NB_FP32_KAHAN)
+        cfg = nb.nb_tile_config(n, ic.n1, nb.NB_FP32_KAHAN)
         print_case("nsplit", nsplit, cfg)
         a = _gpu_forces(nb, ic, "kahan")
     finally:

@@ -92,13 +92,13 @@ def _past_flags(pos, ic):
 
 
 def test_l1_crossing_counts_step_by_step():
-    """Rigid rotation alone moves nothing across the co-rotating L1 plane: random velocity
-    kicks (seeded) make donor elements cross in both directions."""
+    """Rigid rotation alone moves nothing across the co-rotating L1 plane: an overfull donor
+    (R2 = 0.6) with seeded random velocity kicks makes elements cross in both directions."""
     nb = require_gpu()
-    ic = synth.make_binary(6000, 0.5, seed=6, R2=0.45)
+    ic = synth.make_binary(8000, 0.5, seed=6, R2=0.6)
     p, v = ic.f32()
     rng = np.random.default_rng(60)
-    v = (v + rng.normal(0.0, 3.0, size=v.shape)).astype(np.float32)
+    v = (v + rng.normal(0.0, 5.0, size=v.shape)).astype(np.float32)
     s = nb.System(p, v, ic.n1, G=ic.G, m=ic.m, dt=1e-4, D1=ic.D1, D2=ic.D2, q=ic.q, R2_0=ic.R2)
     side = np.zeros(ic.n, dtype=np.int8)
     oracle.l1_count(s.positions().astype(np.float64), ic.n1, ic.q, side, init=True)
