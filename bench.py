@@ -133,8 +133,9 @@ def serving(scale: str) -> dict:
         trace = synth.make_trace()  # 256 requests, 20/s, N 4096..131072, q 0.1..1, 500 steps
         desc = "256 requests, Poisson 20/s, N log-uniform 4096..131072 (x64), q U[0.1,1], 500 steps"
     else:
-        trace = synth.make_trace(count=48, n_max=32768, steps=100)
-        desc = "48 requests, Poisson 20/s, N log-uniform 4096..32768 (x64), q U[0.1,1], 100 steps"
+        trace = synth.make_trace(count=48, rate=200.0, n_max=32768, steps=200)
+        desc = ("48 requests, Poisson 200/s, N log-uniform 4096..32768 (x64), q U[0.1,1], "
+                "200 steps")
     budget = 64 << 30
     server = serve.BatchServer(budget_bytes=budget, round_steps=10)
     t0 = time.perf_counter()

@@ -168,6 +168,13 @@ int nb_tile_config(int64_t n, int64_t n1, int32_t mode, int32_t *ki, int32_t *ns
  * (nsplit = 0 restores the built-in rule). Used by the autotuner. */
 int nb_tile_override(int64_t n_lo, int64_t n_hi, int32_t nsplit);
 
+/* Launch shape of the force kernel for calls issued afterwards (graphs keep the shape they were
+ * captured with): 0 (default) launches one workgroup per work unit and lets the hardware
+ * dispatcher balance them; blocks > 0 launches at most that many workgroups, each looping over
+ * units blockIdx, blockIdx + blocks, ... (a persistent launch). Results are bitwise the same
+ * either way: a unit's arithmetic does not depend on which workgroup runs it. */
+int nb_set_force_grid(int32_t blocks);
+
 void nb_destroy(nb_system *s);
 const char *nb_strerror(int status);
 int nb_version(void);

@@ -63,6 +63,10 @@ def load() -> ctypes.CDLL:
                     "libnbody.so is not built (%s); run python -m paper_2303_12166_amd.build"
                     % _abi.LIB_PATH)
             _lib = _abi.declare(ctypes.CDLL(_abi.LIB_PATH))
+    # measured j-split table for this GPU (see autotune.py); the built-in rule otherwise
+    from .autotune import apply_saved
+
+    apply_saved()
     return _lib
 
 
@@ -193,6 +197,10 @@ def nb_graph_launch(graph: ctypes.c_void_p, stream=None) -> None:
 
 def nb_graph_destroy(graph: ctypes.c_void_p) -> None:
     load().nb_graph_destroy(graph)
+
+
+def nb_set_force_grid(blocks: int) -> None:
+    _check(load().nb_set_force_grid(int(blocks)), "nb_set_force_grid")
 
 
 def nb_destroy(handle: ctypes.c_void_p) -> None:

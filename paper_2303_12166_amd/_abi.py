@@ -34,6 +34,7 @@ EXPORTED = (
     "nb_timing_reset",
     "nb_tile_config",
     "nb_tile_override",
+    "nb_set_force_grid",
     "nb_graph_create",
     "nb_graph_launch",
     "nb_graph_destroy",
@@ -106,6 +107,7 @@ def declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.nb_timing_reset.argtypes = []
     lib.nb_tile_config.argtypes = [_i64, _i64, _i32, P(_i32), P(_i32), P(_i32), P(_i32)]
     lib.nb_tile_override.argtypes = [_i64, _i64, _i32]
+    lib.nb_set_force_grid.argtypes = [_i32]
     lib.nb_graph_create.argtypes = [P(_vp), _i32, _i32, _vp, P(_vp)]
     lib.nb_graph_launch.argtypes = [_vp, _vp]
     lib.nb_graph_destroy.argtypes = [_vp]

@@ -22,6 +22,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 namespace nbk {
 
 // ------------------------------------------------------------------ helpers
@@ -862,10 +864,12 @@ hipError_t launch_gather(const Launch &L, int mode, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_forces(const Launch &L, int mode, hipStream_t s)
+hipError_t launch_forces(const Launch &L, int mode, int max_blocks, hipStream_t s)
 {
     if (L.total_units == 0) return hipSuccess;
-    const dim3 g(grid_for(L.total_units)), b(BT);
+    // max_blocks > 0: persistent launch, each block loops over units u, u + grid, ...
+    const int blocks = max_blocks > 0 ? std::min(L.total_units, max_blocks) : L.total_units;
+    const dim3 g(grid_for(blocks)), b(BT);
     if (mode == 0) {
         hipLaunchKernelGGL((k_force_f32<KI32, false>), g, b, 0, s, L);
     } else if (mode == 1) {

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -198,6 +199,9 @@ struct BatchTable {
 std::mutex g_batch_mu;
 std::vector<BatchTable> g_batches;
 
+// Force-kernel grid: 0 = one block per work unit, > 0 = persistent launch of this many blocks.
+std::atomic<int> g_force_grid{0};
+
 }  // namespace
 
 struct nb_graph {
@@ -244,7 +248,7 @@ int launch_force_timed(const Launch &L, int mode, hipStream_t st, bool need_comb
         NB_TRY(hipEventCreate(&b));
         NB_TRY(hipEventRecord(a, st));
     }
-    NB_TRY(launch_forces(L, mode, st));
+    NB_TRY(launch_forces(L, mode, g_force_grid.load(), st));
     if (timed) {
         NB_TRY(hipEventRecord(b, st));
         std::lock_guard<std::mutex> g(g_timing.mu);
@@ -345,6 +349,13 @@ int nb_tile_config(int64_t n, int64_t n1, int32_t mode, int32_t *ki, int32_t *ns
     if (nsplit) *nsplit = c.nsplit;
     if (iblock) *iblock = c.iblock;
     if (jchunk) *jchunk = c.jchunk;
+    return NB_OK;
+}
+
+int nb_set_force_grid(int32_t blocks)
+{
+    if (blocks < 0) return NB_E_INVAL;
+    g_force_grid.store(blocks);
     return NB_OK;
 }
 
@@ -509,7 +520,7 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
         if (launch_l1_classify(L, p->mode, 1, st) != hipSuccess) { rc = NB_E_HIP; break; }
         if (launch_finalize_l1(L, 1, st) != hipSuccess) { rc = NB_E_HIP; break; }
         if (launch_gather(L, p->mode, st) != hipSuccess) { rc = NB_E_HIP; break; }
-        if (launch_forces(L, p->mode, st) != hipSuccess) { rc = NB_E_HIP; break; }
+        if (launch_forces(L, p->mode, g_force_grid.load(), st) != hipSuccess) { rc = NB_E_HIP; break; }
         if (cfg.nsplit > 1 && launch_combine(L, p->mode, st) != hipSuccess) { rc = NB_E_HIP; break; }
         if (hipStreamSynchronize(st) != hipSuccess) { rc = NB_E_HIP; break; }
     } while (0);

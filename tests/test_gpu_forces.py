@@ -148,3 +148,16 @@ def test_j_split_choices_agree(nsplit):
         nb.nb_tile_override(n, n, 0)
     ref = oracle.accel(_oracle_input(ic, "kahan"), ic.n1, ic.G, ic.m, ic.D1, ic.D2)
     assert force_error(a, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("blocks", [7, 512])
+def test_persistent_launch_is_bitwise_identical(blocks):
+    nb = require_gpu()
+    ic = synth.make_binary(30000, 0.5, seed=4)
+    a0 = _gpu_forces(nb, ic, "kahan")
+    nb.nb_set_force_grid(blocks)
+    try:
+        a1 = _gpu_forces(nb, ic, "kahan")
+    finally:
+        nb.nb_set_force_grid(0)
+    assert np.array_equal(a0, a1)
