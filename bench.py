@@ -39,7 +39,7 @@ WORKLOADS = {
     "c4": dict(n=131072, q=0.8, mode="kahan", steps=200, warmup=5),
 }
 
-KERNEL_NAMES = {"kahan": "k_force_f32<1,true>", "plain": "k_force_f32<1,false>",
+KERNEL_NAMES = {"kahan": "k_force_sym", "plain": "k_force_f32<1,false>",
                 "fp64": "k_force_f64"}
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "force_counters.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2303_12166_amd", "csrc", "nb_kernels.hip")
@@ -158,6 +158,55 @@ def serving(scale: str) -> dict:
     }
 
 
+def precision_study(steps: int) -> dict:
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2303_12166_amd as nb
+    import synth
+
+    n, q = 131072, 0.8
+    ic = synth.make_binary(n, q, seed=0)
+    rng = np.random.default_rng(4)
+    rows = np.unique(np.concatenate([[0, ic.n1 - 1, ic.n1, n - 1],
+                                     rng.integers(0, n, size=252)])).astype(np.int64)
+    p64, _ = ic.f32_as_f64()
+    ref = oracle.accel(p64, ic.n1, ic.G, ic.m, ic.D1, ic.D2, rows=rows)
+    scale = np.linalg.norm(ref, axis=1).max()
+    out = {"workload": "two-star binary, N=131072, q=0.8, dt=1e-4, growth off",
+           "steps": steps, "force_error_rows": int(len(rows)), "modes": {}}
+    for mode in ("plain", "kahan", "fp64"):
+        s = nb.System.from_ic(ic, mode=mode, growth_on=False)
+        a0 = s.accelerations()
+        err = float(np.linalg.norm(a0[rows] - ref, axis=1).max() / scale)
+        d0 = s.diagnostics(with_pe=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < steps:
+            k = min(250, steps - done)
+            s.step(k)
+            s.synchronize()
+            done += k
+            log("precision study %s: %d/%d steps" % (mode, done, steps))
+        t = time.perf_counter() - t0
+        d1 = s.diagnostics(with_pe=True)
+        v = s.velocities().astype(np.float64)
+        s.close()
+        pnorm = ic.m * np.linalg.norm(v, axis=1).sum()
+        out["modes"][mode] = {
+            "force_error_step0": err,
+            "energy_drift": abs(d1["E"] - d0["E"]) / abs(d0["E"]),
+            "momentum_drift": float(np.linalg.norm(d1["P"] - d0["P"]) / pnorm),
+            "angular_momentum_drift": float(np.linalg.norm(d1["L"] - d0["L"])
+                                            / np.linalg.norm(d0["L"])),
+            "seconds": t,
+            "ms_per_step": t / steps * 1e3,
+        }
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,12 +219,27 @@ def main() -> int:
     ap.add_argument("--serve", choices=["none", "small", "full"], default="small",
                     help="serving measurement: 'small' adds a 48-request trace to the main line; "
                          "'full' runs only the 256-request trace (N 4096..131072, 500 steps)")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="N=131072, q=0.8: FP32 plain, FP32 Kahan and FP64 runs of --steps steps "
+                         "(default 2000), step-0 force error vs the FP64 oracle and FP64 drift of "
+                         "E, P and L (donor growth off so that the energy is conserved)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (three times), the reference "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes")
     args = ap.parse_args()
     if args.copy_calibration:
         return copy_calibration()
+    if args.precision_study:
+        import torch
+
+        import paper_2303_12166_amd as nb
+
+        nb.load()
+        torch.cuda.set_device(0)
+        res = precision_study(args.steps or 2000)
+        print(json.dumps({"metric": "precision study (force error, E/P/L drift)", "value": None,
+                          "n_gpus": 1, "data": "synthetic", "precision_study": res}), flush=True)
+        return 0
     if args.serve == "full":
         import torch
 

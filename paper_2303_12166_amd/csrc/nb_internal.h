@@ -17,10 +17,21 @@ namespace nbk {
 #ifndef NB_WAVES_PER_EU
 #define NB_WAVES_PER_EU 8  // > 0: ask the compiler for this many waves per SIMD (VGPR cap)
 #endif
+#ifndef NB_SYM_UNROLL
+#define NB_SYM_UNROLL 1    // groups of four j per unrolled step of the symmetric kernel
+#endif
+#ifndef NB_SYM_WAVES_PER_EU
+#define NB_SYM_WAVES_PER_EU 8
+#endif
 #if NB_WAVES_PER_EU > 0
 #define NB_FORCE_ATTR __attribute__((amdgpu_waves_per_eu(NB_WAVES_PER_EU)))
 #else
 #define NB_FORCE_ATTR
+#endif
+#if NB_SYM_WAVES_PER_EU > 0
+#define NB_SYM_ATTR __attribute__((amdgpu_waves_per_eu(NB_SYM_WAVES_PER_EU)))
+#else
+#define NB_SYM_ATTR
 #endif
 
 constexpr int BT = 256;          // threads per block, every kernel
@@ -89,6 +100,10 @@ struct SysDesc {
     int32_t n_peunits, pad;
     int32_t npad, p1, nalloc, ntiles;  // sorted layout (see above)
     int32_t tunit_begin, pad2;         // prefix offset of this system's tiles in the launch
+    // symmetric FP32 kernel (Kahan mode): work units (row I, chunk c) and reaction partials
+    int32_t *units;       // n_units pairs (I, c)
+    float *react;         // 3 * TJ * ntiles (ntiles - 1) / 2 reaction sums
+    int32_t ch, sym;      // tiles per chunk; 1 when the symmetric kernel is used
 };
 
 // Kernel argument describing one launch over a segment table.

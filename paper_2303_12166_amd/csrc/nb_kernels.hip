@@ -387,6 +387,227 @@ __global__ __launch_bounds__(BT) NB_FORCE_ATTR void k_force_f32(Launch L)
     }
 }
 
+// ------------------------------------------------------------------ FP32 symmetric force kernel
+//
+// Newton's third law halves the pair work: the pair (i, j) with i in tile I and j in a later tile
+// J > I is evaluated once. Row I of the work is the block's 256 i slots against tiles I .. T-1,
+// cut into chunks of `ch` tiles. Within a wave each lane keeps one i element; a tile's 256 j
+// elements are taken as four groups of 64. At step s (0..63) lane l meets element (l - s) mod 64
+// of each group: its position is read from LDS at that rotating offset, and the j accumulator
+// travels with it, moved one lane per step by a DPP wave rotation fused into the update
+// a_j <- rotate(a_j) - s (r_j - r_i). After 64 steps (and one last rotation) every lane holds the
+// summed reaction of the wave's 64 i elements on its own j. The four waves' sums are added in
+// wave order and stored as the reaction of row I on those j. The diagonal tile J = I is
+// evaluated one-sided. k_combine_sym adds, per element, its own row's chunk partials and then
+// the reactions of every lower row, in that order, with Kahan compensation.
+
+constexpr int DPP_WAVE_ROR1 = 0x13C;  // lane l receives lane l - 1 (mod 64)
+
+__device__ __forceinline__ float wave_ror1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), DPP_WAVE_ROR1, 0xf, 0xf, true));
+}
+
+// One-sided diagonal tile from an AoS LDS tile (x, y, z, unused).
+__device__ __forceinline__ void diag_tile(const float4 *__restrict__ sj, IState<1> &I, float c1,
+                                          float nc2)
+{
+    const float eps = 1.0e-24f;
+#pragma unroll 4
+    for (int jj = 0; jj < TJ; ++jj) {
+        const float4 P = sj[jj];
+        const float dx = P.x - I.x[0];
+        const float dy = P.y - I.y[0];
+        const float dz = P.z - I.z[0];
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
+        const float w = __builtin_amdgcn_rsqf(r2);
+        const float w3 = (w * w) * w;
+        const float s = fminf(w3, fmaf(nc2, w, c1));
+        I.ax[0] = fmaf(s, dx, I.ax[0]);
+        I.ay[0] = fmaf(s, dy, I.ay[0]);
+        I.az[0] = fmaf(s, dz, I.az[0]);
+    }
+}
+
+template <bool NEAR>
+__device__ __forceinline__ void sym_tile(const float4 *__restrict__ sj, IState<1> &I, float c1,
+                                         float nc2, float *rwx, float *rwy, float *rwz, int lane)
+{
+    // keep p = s d and the rotated update a_j <- rotate(a_j) - p as separate operations, so that
+    // the rotation folds into the subtraction (a VOP2 instruction with a DPP source)
+#pragma clang fp contract(off)
+    const float eps = 1.0e-24f;
+    float ajx[4] = {0.f, 0.f, 0.f, 0.f}, ajy[4] = {0.f, 0.f, 0.f, 0.f};
+    float ajz[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll NB_SYM_UNROLL
+    for (int st = 0; st < 64; ++st) {
+        const int e = (lane - st) & 63;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const float4 P = sj[g * 64 + e];
+            const float dx = P.x - I.x[0];
+            const float dy = P.y - I.y[0];
+            const float dz = P.z - I.z[0];
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
+            const float w = __builtin_amdgcn_rsqf(r2);
+            const float w3 = (w * w) * w;
+            const float s = NEAR ? fminf(w3, fmaf(nc2, w, c1)) : w3;
+            const float px = s * dx, py = s * dy, pz = s * dz;
+            I.ax[0] += px;
+            I.ay[0] += py;
+            I.az[0] += pz;
+            ajx[g] = wave_ror1(ajx[g]) - px;
+            ajy[g] = wave_ror1(ajy[g]) - py;
+            ajz[g] = wave_ror1(ajz[g]) - pz;
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        // one more rotation brings element l's sum back to lane l
+        rwx[g * 64 + lane] = wave_ror1(ajx[g]);
+        rwy[g * 64 + lane] = wave_ror1(ajy[g]);
+        rwz[g * 64 + lane] = wave_ror1(ajz[g]);
+    }
+}
+
+// Reactions of row I are stored row after row: row I covers slots [TJ (I + 1), npad), three
+// components one after the other.
+__device__ __forceinline__ size_t react_row_offset(int I, int npad)
+{
+    return (size_t)3 * ((size_t)I * npad - (size_t)TJ * I * (I + 1) / 2);
+}
+
+__device__ void force_unit_sym(const SysDesc &S, int I, int c, float4 *sj, float (*rw)[3][TJ])
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const float *__restrict__ XS = static_cast<const float *>(S.xs);
+    const float *__restrict__ YS = static_cast<const float *>(S.ys);
+    const float *__restrict__ ZS = static_cast<const float *>(S.zs);
+    const DevState *st = S.st;
+    const int slot = I * TJ + tid;
+    IState<1> Ist;
+    Ist.x[0] = XS[slot];
+    Ist.y[0] = YS[slot];
+    Ist.z[0] = ZS[slot];
+    Ist.ax[0] = Ist.ay[0] = Ist.az[0] = 0.0f;
+    const bool real = S.perm[slot] >= 0;
+    float lo[3], hi[3];
+    lo[0] = wave_min(real ? Ist.x[0] : INFINITY);
+    lo[1] = wave_min(real ? Ist.y[0] : INFINITY);
+    lo[2] = wave_min(real ? Ist.z[0] : INFINITY);
+    hi[0] = wave_max(real ? Ist.x[0] : -INFINITY);
+    hi[1] = wave_max(real ? Ist.y[0] : -INFINITY);
+    hi[2] = wave_max(real ? Ist.z[0] : -INFINITY);
+    const int istar = I * TJ >= S.p1 ? 1 : 0;
+    const float c1a = st->c1f[istar], nc2a = -st->c2f[istar], far2a = st->far2f[istar];
+    const float c1b = st->c1f[istar + 1], nc2b = -st->c2f[istar + 1], far2b = st->far2f[istar + 1];
+
+    float sumx = 0.f, sumy = 0.f, sumz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+    const int t0 = I + c * S.ch;
+    const int t1 = min(S.ntiles, t0 + S.ch);
+    const int npad = S.npad;
+    float *R = S.react;
+    const size_t roff = react_row_offset(I, npad);
+    const size_t rlen = (size_t)npad - (size_t)TJ * (I + 1);
+    float px = 0.f, py = 0.f, pz = 0.f;
+    if (t0 < t1) {
+        px = XS[t0 * TJ + tid];
+        py = YS[t0 * TJ + tid];
+        pz = ZS[t0 * TJ + tid];
+    }
+    for (int t = t0; t < t1; ++t) {
+        sj[tid] = make_float4(px, py, pz, 0.0f);
+        __syncthreads();
+        if (t + 1 < t1) {
+            px = XS[(t + 1) * TJ + tid];
+            py = YS[(t + 1) * TJ + tid];
+            pz = ZS[(t + 1) * TJ + tid];
+        }
+        const bool jstar = t * TJ >= S.p1;
+        const float c1 = jstar ? c1b : c1a, nc2 = jstar ? nc2b : nc2a;
+        if (t == I) {
+            diag_tile(sj, Ist, c1, nc2);
+        } else {
+            const float *bx = S.tbox + (size_t)t * 8;
+            const float gx = fmaxf(0.0f, fmaxf(bx[0] - hi[0], lo[0] - bx[4]));
+            const float gy = fmaxf(0.0f, fmaxf(bx[1] - hi[1], lo[1] - bx[5]));
+            const float gz = fmaxf(0.0f, fmaxf(bx[2] - hi[2], lo[2] - bx[6]));
+            const float gap2 = gx * gx + gy * gy + gz * gz;
+            const int far = __builtin_amdgcn_readfirstlane(gap2 >= (jstar ? far2b : far2a) ? 1 : 0);
+            if (far) {
+                sym_tile<false>(sj, Ist, 0.f, 0.f, rw[wave][0], rw[wave][1], rw[wave][2], lane);
+            } else {
+                sym_tile<true>(sj, Ist, c1, nc2, rw[wave][0], rw[wave][1], rw[wave][2], lane);
+            }
+            __syncthreads();
+            const size_t at = roff + (size_t)t * TJ + tid - (size_t)TJ * (I + 1);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                R[at + d * rlen] = ((rw[0][d][tid] + rw[1][d][tid]) + rw[2][d][tid]) + rw[3][d][tid];
+            }
+        }
+        kahan_add(sumx, cx, Ist.ax[0]);
+        kahan_add(sumy, cy, Ist.ay[0]);
+        kahan_add(sumz, cz, Ist.az[0]);
+        Ist.ax[0] = Ist.ay[0] = Ist.az[0] = 0.0f;
+        __syncthreads();  // sj and rw are rewritten by the next tile
+    }
+    if (real) {
+        float *P = static_cast<float *>(S.part);
+        const size_t na = S.nalloc;
+        const size_t b = (size_t)c * 3 * na + slot;
+        P[b] = sumx - cx;
+        P[b + na] = sumy - cy;
+        P[b + 2 * na] = sumz - cz;
+    }
+}
+
+__global__ __launch_bounds__(BT) NB_SYM_ATTR void k_force_sym(Launch L)
+{
+    __shared__ float4 sj[TJ];
+    __shared__ __attribute__((aligned(16))) float rw[BT / 64][3][TJ];
+    for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
+        const SysDesc &S = L.sys[find_sys(L, u, false)];
+        const int2 ic = reinterpret_cast<const int2 *>(S.units)[u - S.unit_begin];
+        force_unit_sym(S, ic.x, ic.y, sj, rw);
+    }
+}
+
+// a = G m (sum of the row's chunk partials, then the reactions of rows 0 .. J-1), in that order
+// with Kahan compensation, scattered to the element's own index.
+__global__ __launch_bounds__(BT) void k_combine_sym(Launch L)
+{
+    for (int u = blockIdx.x; u < L.total_tunits; u += gridDim.x) {
+        const SysDesc &S = L.sys[find_tile_sys(L, u)];
+        const int J = u - S.tunit_begin;
+        const int slot = J * TJ + threadIdx.x;
+        const int idx = S.perm[slot];
+        if (idx < 0) continue;
+        const float *P = static_cast<const float *>(S.part);
+        const float *R = S.react;
+        const size_t na = S.nalloc;
+        const int npad = S.npad;
+        const int cj = (S.ntiles - J + S.ch - 1) / S.ch;
+        float out[3];
+        for (int d = 0; d < 3; ++d) {
+            float sum = 0.f, comp = 0.f;
+            for (int c = 0; c < cj; ++c) kahan_add(sum, comp, P[(size_t)c * 3 * na + d * na + slot]);
+            size_t off = 0;
+            size_t len = (size_t)npad - TJ;
+            for (int I = 0; I < J; ++I) {
+                kahan_add(sum, comp, R[off + d * len + slot - (size_t)TJ * (I + 1)]);
+                off += 3 * len;
+                len -= TJ;
+            }
+            out[d] = sum - comp;
+        }
+        const float gm = S.st->gm_f;
+        static_cast<float *>(S.ax)[idx] = gm * out[0];
+        static_cast<float *>(S.ay)[idx] = gm * out[1];
+        static_cast<float *>(S.az)[idx] = gm * out[2];
+    }
+}
+
 // ------------------------------------------------------------------ FP64 force kernel
 
 __device__ __forceinline__ double rsqrt_f64(double r2)
@@ -873,7 +1094,7 @@ hipError_t launch_forces(const Launch &L, int mode, int max_blocks, hipStream_t 
     if (mode == 0) {
         hipLaunchKernelGGL((k_force_f32<KI32, false>), g, b, 0, s, L);
     } else if (mode == 1) {
-        hipLaunchKernelGGL((k_force_f32<KI32, true>), g, b, 0, s, L);
+        hipLaunchKernelGGL(k_force_sym, g, b, 0, s, L);
     } else {
         hipLaunchKernelGGL(k_force_f64, g, b, 0, s, L);
     }
@@ -887,7 +1108,7 @@ hipError_t launch_combine(const Launch &L, int mode, hipStream_t s)
     if (mode == 0) {
         hipLaunchKernelGGL((k_combine<float, false>), g, b, 0, s, L);
     } else if (mode == 1) {
-        hipLaunchKernelGGL((k_combine<float, true>), g, b, 0, s, L);
+        hipLaunchKernelGGL(k_combine_sym, g, b, 0, s, L);
     } else {
         hipLaunchKernelGGL((k_combine<double, false>), g, b, 0, s, L);
     }

@@ -46,6 +46,8 @@ double l1_from_accretor(double q)
 struct TileCfg {
     int ki, nsplit, iblock, jchunk, n_iblocks, n_units, n_ounits;
     int npad, p1, nalloc, ntiles;
+    int sym, ch;            // symmetric kernel (Kahan mode) and its tiles per chunk
+    size_t react_floats;    // reaction partials of the symmetric kernel
 };
 
 struct Override {
@@ -81,6 +83,19 @@ TileCfg tile_config(int64_t n, int64_t n1, int mode)
             if (n >= o.lo && n <= o.hi) ns = o.nsplit;
         }
     }
+    if (mode == NB_FP32_KAHAN && c.ntiles > 0) {
+        // symmetric kernel: row I covers tiles I .. T-1 in chunks of ch tiles; nsplit is the
+        // chunk count of the longest row
+        c.sym = 1;
+        c.ch = std::max(1, (c.ntiles + std::max(ns, 1) - 1) / std::max(ns, 1));
+        c.nsplit = (c.ntiles + c.ch - 1) / c.ch;
+        c.jchunk = c.ch * TJ;
+        int64_t units = 0;
+        for (int k = 1; k <= c.ntiles; ++k) units += (k + c.ch - 1) / c.ch;
+        c.n_units = (int)units;
+        c.react_floats = (size_t)3 * TJ * (size_t)c.ntiles * (size_t)(c.ntiles - 1) / 2;
+        return c;
+    }
     // chunk c covers tiles [c ntiles / nsplit, (c + 1) ntiles / nsplit)
     c.nsplit = c.ntiles > 0 ? std::max(1, std::min(ns, c.ntiles)) : 1;
     c.jchunk = c.ntiles > 0 ? (c.ntiles + c.nsplit - 1) / c.nsplit * TJ : TJ;
@@ -89,7 +104,7 @@ TileCfg tile_config(int64_t n, int64_t n1, int mode)
 }
 
 struct Layout {
-    size_t state, desc, diag, red, pe, log, xs, ys, zs, perm, tbox, part, total;
+    size_t state, desc, diag, red, pe, log, xs, ys, zs, perm, tbox, units, react, part, total;
 };
 
 Layout layout_for(int mode, const TileCfg &c)
@@ -113,8 +128,10 @@ Layout layout_for(int mode, const TileCfg &c)
     L.zs = take((size_t)c.nalloc * elem);
     L.perm = take((size_t)c.nalloc * sizeof(int32_t));
     L.tbox = take((size_t)std::max(c.ntiles, 1) * 8 * sizeof(float));
+    L.units = take(c.sym ? (size_t)c.n_units * 2 * sizeof(int32_t) : 0);
+    L.react = take(c.sym ? c.react_floats * sizeof(float) : 0);
     L.part = off;
-    if (c.nsplit > 1) take((size_t)c.nsplit * 3 * (size_t)c.nalloc * elem);
+    if (c.nsplit > 1 || c.sym) take((size_t)c.nsplit * 3 * (size_t)c.nalloc * elem);
     L.total = off;
     return L;
 }
@@ -314,7 +331,7 @@ Launch build_table(nb_system *const *sys, int32_t n_sys, std::vector<SysDesc> &t
         L.total_units += sys[k]->cfg.n_units;
         L.total_ounits += sys[k]->cfg.n_ounits;
         L.total_tunits += sys[k]->cfg.ntiles;
-        combine = combine || sys[k]->cfg.nsplit > 1;
+        combine = combine || sys[k]->cfg.nsplit > 1 || sys[k]->cfg.sym;
     }
     L.n_sys = n_sys;
     return L;
@@ -424,7 +441,11 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
     d.az = b->az;
     d.side = static_cast<int8_t *>(b->side);
     d.st = s->d_state;
-    d.part = cfg.nsplit > 1 ? base + lay.part : nullptr;
+    d.part = (cfg.nsplit > 1 || cfg.sym) ? base + lay.part : nullptr;
+    d.units = cfg.sym ? reinterpret_cast<int32_t *>(base + lay.units) : nullptr;
+    d.react = cfg.sym ? reinterpret_cast<float *>(base + lay.react) : nullptr;
+    d.ch = cfg.ch;
+    d.sym = cfg.sym;
     d.xs = base + lay.xs;
     d.ys = base + lay.ys;
     d.zs = base + lay.zs;
@@ -507,6 +528,28 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
         }
         if (hipMemcpyAsync(d.perm, perm.data(), perm.size() * sizeof(int32_t),
                            hipMemcpyHostToDevice, st) != hipSuccess) { rc = NB_E_HIP; break; }
+        std::vector<int32_t> units;
+        if (cfg.sym) {
+            // (row, chunk) pairs, full-length chunks first (each row's last chunk may be short)
+            std::vector<std::pair<int, std::pair<int, int>>> order;
+            for (int I = 0; I < cfg.ntiles; ++I) {
+                const int rows = (cfg.ntiles - I + cfg.ch - 1) / cfg.ch;
+                for (int c = 0; c < rows; ++c) {
+                    const int len = std::min(cfg.ch, cfg.ntiles - I - c * cfg.ch);
+                    order.push_back({-len, {I, c}});
+                }
+            }
+            std::stable_sort(order.begin(), order.end(),
+                             [](const auto &a, const auto &b) { return a.first < b.first; });
+            units.reserve(order.size() * 2);
+            for (const auto &o : order) {
+                units.push_back(o.second.first);
+                units.push_back(o.second.second);
+            }
+            if ((int)order.size() != cfg.n_units) { rc = NB_E_INVAL; break; }
+            if (hipMemcpyAsync(d.units, units.data(), units.size() * sizeof(int32_t),
+                               hipMemcpyHostToDevice, st) != hipSuccess) { rc = NB_E_HIP; break; }
+        }
         if (launch_fill_sorted(d.xs, d.ys, d.zs, cfg.nalloc, p->mode, st) != hipSuccess) {
             rc = NB_E_HIP;
             break;
@@ -521,7 +564,10 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
         if (launch_finalize_l1(L, 1, st) != hipSuccess) { rc = NB_E_HIP; break; }
         if (launch_gather(L, p->mode, st) != hipSuccess) { rc = NB_E_HIP; break; }
         if (launch_forces(L, p->mode, g_force_grid.load(), st) != hipSuccess) { rc = NB_E_HIP; break; }
-        if (cfg.nsplit > 1 && launch_combine(L, p->mode, st) != hipSuccess) { rc = NB_E_HIP; break; }
+        if ((cfg.nsplit > 1 || cfg.sym) && launch_combine(L, p->mode, st) != hipSuccess) {
+            rc = NB_E_HIP;
+            break;
+        }
         if (hipStreamSynchronize(st) != hipSuccess) { rc = NB_E_HIP; break; }
     } while (0);
     if (rc != NB_OK) {
@@ -536,7 +582,7 @@ int nb_forces(nb_system *s, void *stream)
 {
     if (!s) return NB_E_INVAL;
     return launch_force_timed(single_launch(s), s->p.mode, static_cast<hipStream_t>(stream),
-                              s->cfg.nsplit > 1);
+                              s->cfg.nsplit > 1 || s->cfg.sym);
 }
 
 int nb_step(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *stream)
@@ -547,7 +593,8 @@ int nb_step(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *stream)
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int mode = sys[0]->p.mode;
     if (n_sys == 1) {
-        return run_steps(single_launch(sys[0]), mode, n_steps, sys[0]->cfg.nsplit > 1, st);
+        return run_steps(single_launch(sys[0]), mode, n_steps,
+                         sys[0]->cfg.nsplit > 1 || sys[0]->cfg.sym, st);
     }
     int device = 0;
     NB_TRY(hipGetDevice(&device));

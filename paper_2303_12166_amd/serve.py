@@ -8,6 +8,12 @@ requests first-come first-served while their device footprint fits the memory bu
 newly admitted systems on a second stream in a worker thread, so admission overlaps the running
 rounds. A request whose footprint exceeds the whole budget is rejected.
 
+Which admitted systems take part in a round is a policy choice. ``"all"`` steps every resident
+system each round (processor sharing: all requests finish together). ``"srpt"`` (default) orders
+the resident systems by remaining work (steps left times N^2) and takes the shortest ones until
+the round's per-step work reaches ``fill`` pair interactions, enough to keep the GPU busy, so short
+requests finish first while large ones still fill the machine.
+
 The one-at-a-time baseline runs the same trace through the plain path: each request, in arrival
 order, is created and stepped alone to completion before the next one starts.
 
@@ -102,7 +108,10 @@ def summarize(records, t0: float = 0.0) -> dict:
 class BatchServer:
     def __init__(self, budget_bytes: int, round_steps: int = 10, max_active: int = 512,
                  mode: str = "kahan", dt: float = 1e-4, use_graphs: bool = True,
-                 keep_digests: bool = True):
+                 keep_digests: bool = True, policy: str = "srpt", fill: float = 1.2e10,
+                 workers: int = 2):
+        if policy not in ("srpt", "all"):
+            raise ValueError("policy must be 'srpt' or 'all'")
         import torch
 
         self.torch = torch
@@ -113,6 +122,9 @@ class BatchServer:
         self.dt = dt
         self.use_graphs = use_graphs
         self.keep_digests = keep_digests
+        self.policy = policy
+        self.fill = float(fill)
+        self.workers = max(1, int(workers))
         self.compute = torch.cuda.Stream()
         self.admit_stream = torch.cuda.Stream()
         self.rounds = 0
@@ -140,12 +152,14 @@ class BatchServer:
         pending = collections.deque(sorted(trace, key=lambda r: (r.t_arrive, r.rid)))
         waiting = collections.deque()
         todo, ready = queue.Queue(), queue.Queue()
-        worker = threading.Thread(target=self._worker, args=(todo, ready), daemon=True)
-        worker.start()
+        workers = [threading.Thread(target=self._worker, args=(todo, ready), daemon=True)
+                   for _ in range(self.workers)]
+        for w in workers:
+            w.start()
         active = []  # [System, Record, remaining]
         reserved = 0
         in_flight = 0
-        graph, graph_key = None, None
+        graphs = {}  # (request ids of the round's systems, k) -> graph
         t0 = time.perf_counter()
 
         def now():
@@ -171,7 +185,6 @@ class BatchServer:
                     rec.status = "admitted"
                     in_flight += 1
                     todo.put((req, rec))
-                changed = False
                 while True:
                     try:
                         req, rec, sysm, err = ready.get_nowait()
@@ -181,7 +194,6 @@ class BatchServer:
                     if err is not None:
                         raise err
                     active.append([sysm, rec, req.steps])
-                    changed = True
                 if not active:
                     # idle: wait for an arrival or a system under construction
                     nxt = pending[0].t_arrive - now() if pending else 0.002
@@ -194,26 +206,35 @@ class BatchServer:
                     elif nxt > 0:
                         time.sleep(min(nxt, 0.05))
                     continue
-                k = min(self.round_steps, min(a[2] for a in active))
-                key = (tuple(id(a[0]) for a in active), k)
+                if self.policy == "srpt":
+                    order = sorted(active, key=lambda a: (a[2] * float(a[1].n) ** 2,
+                                                          a[1].t_arrive, a[1].rid))
+                    chosen, work = [], 0.0
+                    for a in order:
+                        chosen.append(a)
+                        work += float(a[1].n) ** 2
+                        if work >= self.fill:
+                            break
+                else:
+                    chosen = active
+                k = min(self.round_steps, min(a[2] for a in chosen))
+                key = (tuple(a[1].rid for a in chosen), k)
                 if self.use_graphs:
-                    if changed or key != graph_key:
-                        if graph is not None:
-                            nb_graph_destroy(graph)
-                        graph = nb_graph_create([a[0].handle for a in active], k, self.compute)
-                        graph_key = key
+                    graph = graphs.get(key)
+                    if graph is None:
+                        graph = nb_graph_create([a[0].handle for a in chosen], k, self.compute)
+                        graphs[key] = graph
                         self.graphs_built += 1
                     nb_graph_launch(graph, self.compute)
                 else:
                     from . import nb_step
 
-                    nb_step([a[0].handle for a in active], k, self.compute)
+                    nb_step([a[0].handle for a in chosen], k, self.compute)
                 self.compute.synchronize()
                 self.rounds += 1
                 t = now()
-                keep = []
-                retired = False
-                for a in active:
+                retired = []
+                for a in chosen:
                     a[2] -= k
                     if a[2] <= 0:
                         sysm, rec = a[0], a[1]
@@ -221,28 +242,31 @@ class BatchServer:
                         rec.status = "done"
                         if self.keep_digests:
                             rec.digest = state_digest(sysm)
-                        retired = True
-                    else:
-                        keep.append(a)
+                        retired.append(a)
                 if retired:
-                    if graph is not None:
-                        nb_graph_destroy(graph)
-                        graph, graph_key = None, None
-                    for a in active:
-                        if a[2] <= 0:
-                            reserved -= a[1].bytes
-                            a[0].close()
-                    active = keep
+                    gone = {a[1].rid for a in retired}
+                    for gk in [gk for gk in graphs if gone.intersection(gk[0])]:
+                        nb_graph_destroy(graphs.pop(gk))
+                    for a in retired:
+                        reserved -= a[1].bytes
+                        a[0].close()
+                    active = [a for a in active if a[1].rid not in gone]
                     if log:
                         log("t=%.2fs active=%d waiting=%d done=%d" % (
                             t, len(active), len(waiting),
                             sum(r.status == "done" for r in recs.values())))
+                if len(graphs) > 64:  # bound the cache: drop graphs of older rounds
+                    for gk in list(graphs)[:-16]:
+                        if gk != key:
+                            nb_graph_destroy(graphs.pop(gk))
         finally:
-            todo.put(None)
-            worker.join(timeout=60)
-            if graph is not None:
-                self.compute.synchronize()
-                nb_graph_destroy(graph)
+            for _ in workers:
+                todo.put(None)
+            for w in workers:
+                w.join(timeout=60)
+            self.compute.synchronize()
+            for g in graphs.values():
+                nb_graph_destroy(g)
             for a in active:
                 a[0].close()
         return [recs[r.rid] for r in trace]

@@ -70,6 +70,17 @@ def test_scratch_bytes_and_tile_config(nb):
     assert nb.nb_tile_config(262144, 201650, nb.NB_FP32_PLAIN)["nsplit"] == 1
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("n,n1", [(1, 1), (2, 1), (300, 200), (2048, 1366), (65536, 43691),
+                                  (262144, 201650)])
+def test_tile_config_covers_every_slot(nb, mode, n, n1):
+    cfg = nb.nb_tile_config(n, n1, mode)
+    npad = -(-n1 // 256) * 256 + -(-(n - n1) // 256) * 256
+    assert cfg["nsplit"] >= 1 and cfg["jchunk"] % 256 == 0
+    assert cfg["nsplit"] * cfg["jchunk"] >= npad
+    assert cfg["iblock"] == 256 * cfg["ki"]
+
+
 def test_tile_override(nb):
     before = nb.nb_tile_config(100000, 60000, nb.NB_FP32_KAHAN)["nsplit"]
     nb.nb_tile_override(99000, 101000, 3)

@@ -63,12 +63,13 @@ def _small_trace(count=10, steps=30, rate=400.0, seed=5):
                             seed=seed)
 
 
-def test_server_results_equal_sequential_results():
+@pytest.mark.parametrize("policy", ["srpt", "all"])
+def test_server_results_equal_sequential_results(policy):
     require_gpu()
     from paper_2303_12166_amd import serve
 
     trace = _small_trace()
-    server = serve.BatchServer(budget_bytes=8 << 30, round_steps=7)
+    server = serve.BatchServer(budget_bytes=8 << 30, round_steps=7, policy=policy, fill=2e8)
     batched = server.run(trace)
     seq = serve.run_sequential(trace, chunk=11)
     assert all(r.status == "done" for r in batched)
