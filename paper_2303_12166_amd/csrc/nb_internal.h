@@ -21,7 +21,7 @@ namespace nbk {
 #define NB_SYM_UNROLL 1    // groups of four j per unrolled step of the symmetric kernel
 #endif
 #ifndef NB_SYM_WAVES_PER_EU
-#define NB_SYM_WAVES_PER_EU 8
+#define NB_SYM_WAVES_PER_EU 6
 #endif
 #if NB_WAVES_PER_EU > 0
 #define NB_FORCE_ATTR __attribute__((amdgpu_waves_per_eu(NB_WAVES_PER_EU)))

@@ -592,9 +592,23 @@ __global__ __launch_bounds__(BT) void k_combine_sym(Launch L)
         for (int d = 0; d < 3; ++d) {
             float sum = 0.f, comp = 0.f;
             for (int c = 0; c < cj; ++c) kahan_add(sum, comp, P[(size_t)c * 3 * na + d * na + slot]);
+            // rows are read eight at a time (independent loads in flight), then added in row
+            // order; the arithmetic is the same as one row at a time
             size_t off = 0;
             size_t len = (size_t)npad - TJ;
-            for (int I = 0; I < J; ++I) {
+            int I = 0;
+            for (; I + 8 <= J; I += 8) {
+                float v[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    v[k] = R[off + d * len + slot - (size_t)TJ * (I + k + 1)];
+                    off += 3 * len;
+                    len -= TJ;
+                }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) kahan_add(sum, comp, v[k]);
+            }
+            for (; I < J; ++I) {
                 kahan_add(sum, comp, R[off + d * len + slot - (size_t)TJ * (I + 1)]);
                 off += 3 * len;
                 len -= TJ;
