@@ -52,6 +52,11 @@ class OrcState(ctypes.Structure):
         ("growth_on", ctypes.c_int32),
         ("growth_stopped", ctypes.c_int32),
         ("step", ctypes.c_int64),
+        ("law", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+        ("eps", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("beta", ctypes.c_double),
     ]
 
 
@@ -82,6 +87,18 @@ def _load():
             lib.orc_pair_force.argtypes = [ctypes.c_double] * 5
             lib.orc_pair_potential.restype = ctypes.c_double
             lib.orc_pair_potential.argtypes = [ctypes.c_double] * 5
+            lib.orc_overlap_volume.restype = ctypes.c_double
+            lib.orc_overlap_volume.argtypes = [ctypes.c_double] * 2
+            lib.orc_paper_force.restype = ctypes.c_double
+            lib.orc_paper_force.argtypes = [ctypes.c_double] * 9
+            lib.orc_paper_potential.restype = ctypes.c_double
+            lib.orc_paper_potential.argtypes = [ctypes.c_double] * 7
+            lib.orc_accel_rows_paper.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int64,
+                                                 ctypes.c_int64] + [ctypes.c_double] * 7 + [
+                                                 _i64p, ctypes.c_int64, _dp, _dp, _dp]
+            lib.orc_paper_pe.restype = ctypes.c_double
+            lib.orc_paper_pe.argtypes = [_dp, _dp, _dp, ctypes.c_int64, ctypes.c_int64] + [
+                ctypes.c_double] * 6
             lib.orc_roche_lobe.restype = ctypes.c_double
             lib.orc_roche_lobe.argtypes = [ctypes.c_double]
             lib.orc_l1_point.restype = ctypes.c_double
@@ -128,6 +145,51 @@ def pair_force(r: float, D: float, G: float = 1.0, mi: float = 1.0, mj: float = 
 
 def pair_potential(r: float, D: float, G: float = 1.0, mi: float = 1.0, mj: float = 1.0) -> float:
     return float(_load().orc_pair_potential(r, D, G, mi, mj))
+
+
+def overlap_volume(r: float, R: float) -> float:
+    """Lens volume of two spheres of radius R at centre distance r (eqs. 5-6, read with r^3/12)."""
+    return float(_load().orc_overlap_volume(r, R))
+
+
+def paper_force(r: float, vr: float, R: float, G: float = 1.0, mi: float = 1.0, mj: float = 1.0,
+                eps: float = 0.0, gamma: float = 0.0, beta: float = 1.0) -> float:
+    """Attractive magnitude of eqs. (4)-(6); vr < 0 means the pair converges."""
+    return float(_load().orc_paper_force(r, vr, R, G, mi, mj, eps, gamma, beta))
+
+
+def paper_potential(r: float, R: float, G: float = 1.0, mi: float = 1.0, mj: float = 1.0,
+                    eps: float = 0.0, gamma: float = 0.0) -> float:
+    return float(_load().orc_paper_potential(r, R, G, mi, mj, eps, gamma))
+
+
+def accel_paper(pos, vel, n1, G, m, D1, D2, eps, gamma, beta, rows=None) -> np.ndarray:
+    """All-pairs acceleration under eqs. (4)-(6); returns (k, 3) float64."""
+    lib = _load()
+    pos = np.asarray(pos, dtype=np.float64)
+    vel = np.asarray(vel, dtype=np.float64)
+    n = pos.shape[0]
+    cols = [_col(pos, 0), _col(pos, 1), _col(pos, 2), _col(vel, 0), _col(vel, 1), _col(vel, 2)]
+    if rows is None:
+        k, rp = n, None
+    else:
+        rr = np.ascontiguousarray(rows, dtype=np.int64)
+        if rr.size and (rr.min() < 0 or rr.max() >= n):
+            raise IndexError("row index out of range")
+        k, rp = rr.size, _p(rr, _i64p)
+    ax, ay, az = np.zeros(k), np.zeros(k), np.zeros(k)
+    if k:
+        lib.orc_accel_rows_paper(*[_p(c) for c in cols], n, int(n1), G, m, D1, D2, eps, gamma,
+                                 beta, rp, k, _p(ax), _p(ay), _p(az))
+    return np.stack([ax, ay, az], axis=1)
+
+
+def paper_pe(pos, n1, G, m, D1, D2, eps, gamma) -> float:
+    lib = _load()
+    pos = np.asarray(pos, dtype=np.float64)
+    cols = [_col(pos, 0), _col(pos, 1), _col(pos, 2)]
+    return float(lib.orc_paper_pe(*[_p(c) for c in cols], pos.shape[0], int(n1), G, m, D1, D2,
+                                  eps, gamma))
 
 
 def roche_lobe(q: float) -> float:
@@ -207,7 +269,7 @@ class Run:
     """FP64 kick-drift-kick run with donor growth and L1 counting."""
 
     def __init__(self, pos, vel, n1, G, m, dt, D1, D2, q, a=1.0, R2_0=0.2, growth_rate=1e-4,
-                 growth_on=True, D2_0=None):
+                 growth_on=True, D2_0=None, law=0, eps=0.0, gamma=0.0, beta=1.0):
         pos = np.asarray(pos, dtype=np.float64)
         vel = np.asarray(vel, dtype=np.float64)
         self.n = pos.shape[0]
@@ -217,7 +279,8 @@ class Run:
         self.state = OrcState(n=self.n, n1=int(n1), G=G, m=m, dt=dt, D1=D1, D2=D2, q=q, a=a,
                               R2_0=R2_0, D2_0=D2 if D2_0 is None else D2_0,
                               growth_rate=growth_rate, growth_on=int(bool(growth_on)),
-                              growth_stopped=0, step=0)
+                              growth_stopped=0, step=0, law=int(law), pad=0, eps=eps,
+                              gamma=gamma, beta=beta)
         self._inited = False
 
     def advance(self, steps: int):

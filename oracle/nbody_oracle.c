@@ -26,6 +26,12 @@
  *    around eq. 2), found by bisection of the axial derivative.
  *  - FP64 diagnostics: centre of mass, linear and angular momentum, kinetic, potential and total
  *    energy.
+ *  - the paper's own element law, eqs. (4)-(6), as a second law: softened attraction
+ *    G mi mj / (r + eps)^2 everywhere; for elements in contact (r < 2R) minus a repulsion
+ *    gamma V(r) proportional to the overlap volume V of two spheres of radius R, at full strength
+ *    while the pair converges ((v_j - v_i).(r_j - r_i) < 0) and reduced by the factor beta
+ *    otherwise. The printed volume term r^2/12 is read as r^3/12, so that V vanishes at r = 2R.
+ *    R is half the pair's element diameter.
  */
 #include <math.h>
 #include <stdint.h>
@@ -90,6 +96,44 @@ static double pair_diameter(int64_t i, int64_t j, int64_t n1, double D1, double 
     return si ? D2 : D1;
 }
 
+/* ---------------------------------------------------------------- paper's law, eqs. (4)-(6) */
+
+static const double ORC_PI = 3.14159265358979323846;
+
+/* Overlap volume of two spheres of radius R whose centres are r apart (0 for r >= 2R):
+ * pi (4/3 R^3 - R^2 r + r^3 / 12). */
+double orc_overlap_volume(double r, double R)
+{
+    if (r >= 2.0 * R) return 0.0;
+    return ORC_PI * (4.0 / 3.0 * R * R * R - R * R * r + r * r * r / 12.0);
+}
+
+/* Attractive magnitude of eqs. (4)-(6). vr is the radial relative velocity
+ * (v_j - v_i).(r_j - r_i) / r; the pair converges when vr < 0. */
+double orc_paper_force(double r, double vr, double R, double G, double mi, double mj, double eps,
+                       double gamma, double beta)
+{
+    double f = G * mi * mj / ((r + eps) * (r + eps));
+    if (r < 2.0 * R) {
+        double g = vr < 0.0 ? gamma : gamma * beta;
+        f -= g * orc_overlap_volume(r, R);
+    }
+    return f;
+}
+
+/* Potential of the converging branch (beta = 1): softened gravity plus the primitive of the
+ * overlap repulsion, gamma pi (R^4 - 4/3 R^3 r + R^2 r^2 / 2 - r^4 / 48) for r < 2R. */
+double orc_paper_potential(double r, double R, double G, double mi, double mj, double eps,
+                           double gamma)
+{
+    double u = -G * mi * mj / (r + eps);
+    if (r < 2.0 * R) {
+        u += gamma * ORC_PI * (R * R * R * R - 4.0 / 3.0 * R * R * R * r + R * R * r * r / 2.0
+                             - r * r * r * r / 48.0);
+    }
+    return u;
+}
+
 /* ---------------------------------------------------------------- all-pairs acceleration */
 
 /* a_i = sum_{j != i, r_ij > 0} (f(r_ij) / m) (r_j - r_i) / r_ij for the requested rows.
@@ -120,6 +164,62 @@ void orc_accel_rows(const double *x, const double *y, const double *z, int64_t n
         ay[k] = sy;
         az[k] = sz;
     }
+}
+
+/* a_i under eqs. (4)-(6): like orc_accel_rows, with the pair radius R = D_ij / 2 and the radial
+ * relative velocity taken from vx, vy, vz. */
+void orc_accel_rows_paper(const double *x, const double *y, const double *z, const double *vx,
+                          const double *vy, const double *vz, int64_t n, int64_t n1, double G,
+                          double m, double D1, double D2, double eps, double gamma, double beta,
+                          const int64_t *rows, int64_t nrows, double *ax, double *ay, double *az)
+{
+    int64_t k;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (k = 0; k < nrows; ++k) {
+        int64_t i = rows ? rows[k] : k;
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = x[j] - x[i];
+            double dy = y[j] - y[i];
+            double dz = z[j] - z[i];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (r == 0.0) continue;
+            double vr = ((vx[j] - vx[i]) * dx + (vy[j] - vy[i]) * dy + (vz[j] - vz[i]) * dz) / r;
+            double R = 0.5 * pair_diameter(i, j, n1, D1, D2);
+            double f = orc_paper_force(r, vr, R, G, m, m, eps, gamma, beta);
+            double g = (f / m) / r;
+            sx += g * dx;
+            sy += g * dy;
+            sz += g * dz;
+        }
+        ax[k] = sx;
+        ay[k] = sy;
+        az[k] = sz;
+    }
+}
+
+/* Potential energy sum_{i<j} of the converging-branch potential of eqs. (4)-(6). */
+double orc_paper_pe(const double *x, const double *y, const double *z, int64_t n, int64_t n1,
+                    double G, double m, double D1, double D2, double eps, double gamma)
+{
+    double *row = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    int64_t i;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int64_t j = i + 1; j < n; ++j) {
+            double dx = x[j] - x[i], dy = y[j] - y[i], dz = z[j] - z[i];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (r == 0.0) continue;
+            s += orc_paper_potential(r, 0.5 * pair_diameter(i, j, n1, D1, D2), G, m, m, eps, gamma);
+        }
+        row[i] = s;
+    }
+    double pe = 0.0;
+    for (i = 0; i < n; ++i) pe += row[i];
+    free(row);
+    return pe;
 }
 
 /* Force on element i from element j alone (f_ij as a vector), for antisymmetry checks. */
@@ -284,7 +384,23 @@ typedef struct {
     int32_t growth_on;
     int32_t growth_stopped;
     int64_t step;        /* completed steps */
+    int32_t law;         /* 0: conservative contact law; 1: eqs. (4)-(6) */
+    int32_t pad;
+    double eps, gamma, beta;  /* parameters of eqs. (4)-(6) */
 } orc_state;
+
+/* Accelerations of every element under the state's law (velocity-dependent for law 1). */
+static void accel_all(const orc_state *s, const double *x, const double *y, const double *z,
+                      const double *vx, const double *vy, const double *vz, double *ax,
+                      double *ay, double *az)
+{
+    if (s->law == 1) {
+        orc_accel_rows_paper(x, y, z, vx, vy, vz, s->n, s->n1, s->G, s->m, s->D1, s->D2, s->eps,
+                             s->gamma, s->beta, NULL, s->n, ax, ay, az);
+    } else {
+        orc_accel_rows(x, y, z, s->n, s->n1, s->G, s->m, s->D1, s->D2, NULL, s->n, ax, ay, az);
+    }
+}
 
 /* Donor growth after a step: while the donor's nominal radius R2_0 D2 / D2_0 is at most
  * r_L(q) a, its element diameter grows by (1 + rate); the first time it exceeds the lobe, growth
@@ -313,7 +429,7 @@ void orc_run(orc_state *s, double *x, double *y, double *z, double *vx, double *
     double *az = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
     int32_t c[3];
     if (init_side && side) orc_l1_count(x, y, z, n, s->n1, s->q, side, 1, c);
-    orc_accel_rows(x, y, z, n, s->n1, s->G, s->m, s->D1, s->D2, NULL, n, ax, ay, az);
+    accel_all(s, x, y, z, vx, vy, vz, ax, ay, az);
     double h = 0.5 * s->dt;
     for (int64_t st = 0; st < steps; ++st) {
         for (int64_t i = 0; i < n; ++i) {
@@ -324,7 +440,8 @@ void orc_run(orc_state *s, double *x, double *y, double *z, double *vx, double *
             y[i] += s->dt * vy[i];
             z[i] += s->dt * vz[i];
         }
-        orc_accel_rows(x, y, z, n, s->n1, s->G, s->m, s->D1, s->D2, NULL, n, ax, ay, az);
+        /* for law 1 the velocities seen by the force are the half-step ones */
+        accel_all(s, x, y, z, vx, vy, vz, ax, ay, az);
         for (int64_t i = 0; i < n; ++i) {
             vx[i] += h * ax[i];
             vy[i] += h * ay[i];

@@ -1,0 +1,139 @@
+"""Pins of the oracle's second law, eqs. (4)-(6) (softened attraction, overlap-volume repulsion,
+weaker while the pair is not converging)."""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+R = 0.05
+G, M = 1.0, 0.01
+
+
+def test_overlap_volume_matches_lens_formula_and_limits(orc):
+    # two spheres of radius R: V = pi (4R + r)(2R - r)^2 / 12 (a different closed form)
+    for r in np.linspace(0.0, 2 * R, 11):
+        lens = math.pi * (4 * R + r) * (2 * R - r) ** 2 / 12
+        assert orc.overlap_volume(r, R) == pytest.approx(lens, rel=1e-12, abs=1e-18)
+    assert orc.overlap_volume(0.0, R) == pytest.approx(4 / 3 * math.pi * R**3, rel=1e-15)
+    assert orc.overlap_volume(2 * R, R) == 0.0
+    assert orc.overlap_volume(3 * R, R) == 0.0
+
+
+def test_overlap_volume_monte_carlo():
+    import oracle
+
+    rng = np.random.default_rng(0)
+    r = 0.7 * R
+    pts = rng.uniform(-R, R, size=(400000, 3))  # box around sphere 1 (centre 0)
+    in1 = (pts**2).sum(axis=1) <= R * R
+    in2 = ((pts - [r, 0, 0]) ** 2).sum(axis=1) <= R * R
+    mc = (in1 & in2).mean() * (2 * R) ** 3
+    assert oracle.overlap_volume(r, R) == pytest.approx(mc, rel=0.01)
+
+
+def test_softened_far_field(orc):
+    eps = 0.003
+    f1 = orc.paper_force(3 * R, 0.0, R, G, M, M, eps, 50.0, 0.5)
+    f2 = orc.paper_force(5 * R, 0.0, R, G, M, M, eps, 50.0, 0.5)
+    assert f1 / f2 == pytest.approx(((5 * R + eps) / (3 * R + eps)) ** 2, rel=1e-14)
+    assert f1 == pytest.approx(G * M * M / (3 * R + eps) ** 2, rel=1e-15)
+
+
+def test_converging_repulsion_is_full_and_diverging_reduced(orc):
+    eps, gamma, beta = 0.001, 50.0, 0.3
+    for r in (0.3 * R, R, 1.7 * R):
+        grav = orc.paper_force(r, 0.0, R, G, M, M, eps, 0.0, 1.0)  # gamma = 0: gravity alone
+        conv = orc.paper_force(r, -1.0, R, G, M, M, eps, gamma, beta)
+        div = orc.paper_force(r, +1.0, R, G, M, M, eps, gamma, beta)
+        assert (grav - conv) / (grav - div) == pytest.approx(1 / beta, rel=1e-12)
+        assert grav - conv == pytest.approx(gamma * orc.overlap_volume(r, R), rel=1e-12)
+
+
+def test_potential_derivative_on_converging_branch(orc):
+    eps, gamma = 0.002, 80.0
+    for r in np.concatenate([np.linspace(0.1 * R, 1.95 * R, 8), np.linspace(2.05 * R, 6 * R, 5)]):
+        h = 1e-7 * R
+        dU = (orc.paper_potential(r + h, R, G, M, M, eps, gamma)
+              - orc.paper_potential(r - h, R, G, M, M, eps, gamma)) / (2 * h)
+        f = orc.paper_force(r, -1.0, R, G, M, M, eps, gamma, 0.5)
+        assert dU == pytest.approx(f, rel=2e-6, abs=1e-9)
+    # continuous at contact
+    assert orc.paper_potential(2 * R * (1 - 1e-13), R, G, M, M, eps, gamma) == pytest.approx(
+        -G * M * M / (2 * R + eps), rel=1e-9)
+
+
+def _head_on(orc, beta, steps=4000, dt=2e-4):
+    # two elements approaching along x at speed 1 each, starting 4R apart; weak gravity
+    pos = np.array([[-2 * R, 0.0, 0.0], [2 * R, 0.0, 0.0]])
+    vel = np.array([[1.0, 0.0, 0.0], [-1.0, 0.0, 0.0]])
+    gamma = 2000.0
+    run = orc.Run(pos, vel, 1, 1e-6, M, dt, 2 * R, 2 * R, 1.0, growth_on=False, law=1,
+                  eps=1e-4, gamma=gamma, beta=beta)
+
+    def energy():
+        p, v = run.pos, run.vel
+        r = np.linalg.norm(p[1] - p[0])
+        ke = 0.5 * M * (v * v).sum()
+        return ke + orc.paper_potential(r, R, 1e-6, M, M, 1e-4, gamma)
+
+    E0 = energy()
+    Es, P = [E0], []
+    for _ in range(40):
+        run.advance(steps // 40)
+        Es.append(energy())
+        P.append((M * run.vel).sum(axis=0))
+    return run, np.array(Es), np.array(P)
+
+
+def test_head_on_collision_elastic_when_beta_is_one(orc):
+    run, E, P = _head_on(orc, 1.0)
+    v = run.vel
+    assert v[0][0] < 0 < v[1][0]  # they bounced
+    assert abs(v[1][0]) == pytest.approx(1.0, rel=2e-3)  # elastic: speed restored
+    assert np.abs(E - E[0]).max() < 2e-3 * abs(E[0])
+    assert np.abs(P).max() < 1e-15
+
+
+def test_head_on_collision_loses_energy_when_beta_below_one(orc):
+    run, E, P = _head_on(orc, 0.25)
+    v = run.vel
+    assert v[0][0] < 0 < v[1][0]
+    out = abs(v[1][0])
+    assert 0.2 < out < 0.8  # inelastic rebound
+    assert E[-1] < E[0] * (1 - 0.3)  # energy lost in the contact
+    assert np.all(np.diff(E) <= 1e-4 * abs(E[0]))  # never gained beyond integrator noise
+    assert np.abs(P).max() < 1e-15
+
+
+def test_c_oracle_matches_numpy_transcription(orc):
+    from oracle import np_ref
+
+    ic = synth.make_binary(300, 0.5, seed=3)
+    p, v = ic.f32_as_f64()
+    rng = np.random.default_rng(1)
+    v = v + rng.normal(0.0, 0.5, size=v.shape)
+    kw = dict(eps=0.1 * ic.D1, gamma=30.0 * ic.m**2 / ic.D1**5, beta=0.4)
+    a = orc.accel_paper(p, v, ic.n1, 1.0, ic.m, ic.D1, ic.D2, **kw)
+    b = np_ref.accel_dense_paper(p, v, ic.n1, 1.0, ic.m, ic.D1, ic.D2, **kw)
+    assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
+
+
+def test_reduces_to_newton_without_softening_or_contact(orc):
+    ic = synth.make_binary(200, 0.5, seed=2)
+    p, v = ic.f32_as_f64()
+    tiny = 1e-9  # diameters far below every separation: no contacts
+    a = orc.accel_paper(p, v, ic.n1, 1.0, ic.m, tiny, tiny, 0.0, 5.0, 0.5)
+    b = orc.accel(p, ic.n1, 1.0, ic.m, tiny, tiny)
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+
+
+def test_total_force_vanishes_with_random_velocities(orc):
+    ic = synth.make_binary(1000, 0.5, seed=6)
+    p, v = ic.f32_as_f64()
+    v = v + np.random.default_rng(2).normal(0.0, 1.0, size=v.shape)
+    a = orc.accel_paper(p, v, ic.n1, 1.0, ic.m, ic.D1, ic.D2, 0.05 * ic.D1,
+                        20.0 * ic.m**2 / ic.D1**5, 0.5)
+    assert np.abs(a.sum(axis=0)).max() < 1e-12 * np.abs(a).sum()
