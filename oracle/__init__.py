@@ -113,6 +113,10 @@ def _load():
                                             ctypes.c_int64, ctypes.c_int64, _dp]
             lib.orc_l1_count.argtypes = [_dp, _dp, _dp, ctypes.c_int64, ctypes.c_int64,
                                          ctypes.c_double, _i8p, ctypes.c_int, _i32p]
+            lib.orc_retention.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int64,
+                                          ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, _i32p]
+            lib.orc_retention.restype = None
             lib.orc_diag.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int64, ctypes.c_int64,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_int, _dp]
@@ -250,6 +254,18 @@ def l1_count(pos: np.ndarray, n1: int, q: float, side=None, init: bool = False):
         sp = _p(side, _i8p)
     lib.orc_l1_count(_p(x), _p(y), _p(z), n, int(n1), q, sp, int(bool(init)), _p(out, _i32p))
     return int(out[0]), int(out[1]), int(out[2])
+
+
+def retention(pos: np.ndarray, vel: np.ndarray, n1: int, G: float, m: float, q: float):
+    """Returns (n_past, n_bound): donor elements past L1, and those of them bound to the accretor."""
+    lib = _load()
+    pos = np.asarray(pos, dtype=np.float64)
+    vel = np.asarray(vel, dtype=np.float64)
+    n = pos.shape[0]
+    cols = [_col(pos, 0), _col(pos, 1), _col(pos, 2), _col(vel, 0), _col(vel, 1), _col(vel, 2)]
+    out = np.zeros(2, dtype=np.int32)
+    lib.orc_retention(*[_p(c) for c in cols], n, int(n1), G, m, q, _p(out, _i32p))
+    return int(out[0]), int(out[1])
 
 
 def diag(pos: np.ndarray, vel: np.ndarray, n1: int, G: float, m: float, D1: float, D2: float,

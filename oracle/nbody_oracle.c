@@ -325,6 +325,40 @@ void orc_l1_count(const double *x, const double *y, const double *z, int64_t n, 
     out[2] = bwd;
 }
 
+/* Accretor-side retention of transferred elements. A donor element counts as transferred when it
+ * is past the L1 plane (the test of orc_l1_count), and as retained when it is also bound to the
+ * accretor taken as a point mass M1 = n1 m at its centre of mass C1 moving with its mean velocity
+ * V1: |v - V1|^2 / 2 - G M1 / |r - C1| < 0. out = {n_past, n_bound}. */
+void orc_retention(const double *x, const double *y, const double *z, const double *vx,
+                   const double *vy, const double *vz, int64_t n, int64_t n1, double G,
+                   double m, double q, int32_t out[2])
+{
+    double c1[3], c2[3], v1[3], v2[3];
+    star_centres(x, y, z, n, n1, c1, c2);
+    star_centres(vx, vy, vz, n, n1, v1, v2); /* mean velocities, same index-order sums */
+    double e[3] = {c2[0] - c1[0], c2[1] - c1[1], c2[2] - c1[2]};
+    double d = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    int32_t past = 0, bound = 0;
+    if (n1 > 0 && n > n1 && d > 0.0) {
+        e[0] /= d;
+        e[1] /= d;
+        e[2] /= d;
+        double xi_l1 = orc_l1_point(q) * d;
+        double gm1 = G * m * (double)n1;
+        for (int64_t i = n1; i < n; ++i) {
+            double rx = x[i] - c1[0], ry = y[i] - c1[1], rz = z[i] - c1[2];
+            if (!(rx * e[0] + ry * e[1] + rz * e[2] < xi_l1)) continue;
+            past++;
+            double ux = vx[i] - v1[0], uy = vy[i] - v1[1], uz = vz[i] - v1[2];
+            double r = sqrt(rx * rx + ry * ry + rz * rz);
+            double energy = 0.5 * (ux * ux + uy * uy + uz * uz) - gm1 / r;
+            if (energy < 0.0) bound++;
+        }
+    }
+    out[0] = past;
+    out[1] = bound;
+}
+
 /* ---------------------------------------------------------------- diagnostics */
 
 /* out = {com[3], P[3], L[3], KE, PE, E}. PE = sum_{i<j} U(r_ij) when with_pe, else 0. */
