@@ -121,7 +121,8 @@ def _load():
                                      ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_int, _dp]
             lib.orc_run.argtypes = [ctypes.POINTER(OrcState), _dp, _dp, _dp, _dp, _dp, _dp, _i8p,
-                                    ctypes.c_int, ctypes.c_int64, _i32p, _dp]
+                                    ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int64,
+                                    _i32p, _dp]
             _lib = lib
     return _lib
 
@@ -292,6 +293,8 @@ class Run:
         self.cols = [_col(pos, 0), _col(pos, 1), _col(pos, 2),
                      _col(vel, 0), _col(vel, 1), _col(vel, 2)]
         self.side = np.zeros(self.n, dtype=np.int8)
+        # acceleration of the current state, carried from one advance() to the next
+        self.acc = [np.zeros(max(self.n, 1)) for _ in range(3)]
         self.state = OrcState(n=self.n, n1=int(n1), G=G, m=m, dt=dt, D1=D1, D2=D2, q=q, a=a,
                               R2_0=R2_0, D2_0=D2 if D2_0 is None else D2_0,
                               growth_rate=growth_rate, growth_on=int(bool(growth_on)),
@@ -305,7 +308,8 @@ class Run:
         counts = np.zeros((max(steps, 1), 3), dtype=np.int32)
         d2 = np.zeros(max(steps, 1))
         lib.orc_run(ctypes.byref(self.state), *[_p(c) for c in self.cols], _p(self.side, _i8p),
-                    int(not self._inited), int(steps), _p(counts, _i32p), _p(d2))
+                    int(not self._inited), *[_p(a) for a in self.acc], int(self._inited),
+                    int(steps), _p(counts, _i32p), _p(d2))
         self._inited = True
         return counts[:steps], d2[:steps]
 

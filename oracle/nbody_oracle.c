@@ -452,18 +452,20 @@ static void growth_update(orc_state *s)
 
 /* Advance `steps` kick-drift-kick leap-frog steps. x, v (inout) are FP64; side (inout, n bytes,
  * only donor entries used) carries L1 sides; when init_side != 0 the sides are first set from the
- * initial positions. counts (optional, steps x 3) receives the per-step L1 counts; d2_log
- * (optional, steps) the donor diameter after each step's growth update. */
+ * initial positions. ax, ay, az (inout, n each) hold the acceleration of the current state: with
+ * have_accel == 0 it is evaluated first (a(x, v) of the given state), otherwise the values from
+ * the previous call are used, so that runs split over several calls equal one long run (under
+ * law 1 the acceleration at the end of a step was evaluated with the half-step velocities).
+ * counts (optional, steps x 3) receives the per-step L1 counts; d2_log (optional, steps) the
+ * donor diameter after each step's growth update. */
 void orc_run(orc_state *s, double *x, double *y, double *z, double *vx, double *vy, double *vz,
-             int8_t *side, int init_side, int64_t steps, int32_t *counts, double *d2_log)
+             int8_t *side, int init_side, double *ax, double *ay, double *az, int have_accel,
+             int64_t steps, int32_t *counts, double *d2_log)
 {
     int64_t n = s->n;
-    double *ax = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
-    double *ay = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
-    double *az = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
     int32_t c[3];
     if (init_side && side) orc_l1_count(x, y, z, n, s->n1, s->q, side, 1, c);
-    accel_all(s, x, y, z, vx, vy, vz, ax, ay, az);
+    if (!have_accel) accel_all(s, x, y, z, vx, vy, vz, ax, ay, az);
     double h = 0.5 * s->dt;
     for (int64_t st = 0; st < steps; ++st) {
         for (int64_t i = 0; i < n; ++i) {
@@ -491,7 +493,4 @@ void orc_run(orc_state *s, double *x, double *y, double *z, double *vx, double *
         if (d2_log) d2_log[st] = s->D2;
         s->step++;
     }
-    free(ax);
-    free(ay);
-    free(az);
 }

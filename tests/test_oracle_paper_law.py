@@ -137,3 +137,22 @@ def test_total_force_vanishes_with_random_velocities(orc):
     a = orc.accel_paper(p, v, ic.n1, 1.0, ic.m, ic.D1, ic.D2, 0.05 * ic.D1,
                         20.0 * ic.m**2 / ic.D1**5, 0.5)
     assert np.abs(a.sum(axis=0)).max() < 1e-12 * np.abs(a).sum()
+
+
+def test_split_run_equals_one_run(orc):
+    """Under law 1 the first kick of a step uses the acceleration evaluated at the end of the
+    previous step (with half-step velocities), so advancing 1 + 2 + 3 steps equals advancing 6."""
+    rng = np.random.default_rng(12)
+    n, n1 = 300, 200
+    pos = rng.uniform(-0.1, 0.1, size=(n, 3))
+    pos[n1:] += np.array([0.3, 0.0, 0.0])
+    vel = rng.normal(0.0, 0.3, size=(n, 3))
+    kw = dict(G=1.0, m=1.0 / n, dt=1e-4, D1=0.03, D2=0.025, q=0.5, a=0.3, R2_0=0.1,
+              law=1, eps=0.003, gamma=2e3, beta=0.3)
+    one = orc.Run(pos, vel, n1, **kw)
+    c_one, _ = one.advance(6)
+    split = orc.Run(pos, vel, n1, **kw)
+    parts = [split.advance(k)[0] for k in (1, 2, 3)]
+    assert np.array_equal(one.pos, split.pos)
+    assert np.array_equal(one.vel, split.vel)
+    assert np.array_equal(c_one, np.concatenate(parts))
