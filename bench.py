@@ -40,7 +40,8 @@ WORKLOADS = {
 }
 
 KERNEL_NAMES = {"kahan": "k_force_sym", "plain": "k_force_f32<1,false>",
-                "fp64": "k_force_f64"}
+                "fp64": "k_force_f64<0>"}
+PAPER_KERNEL_NAMES = {"kahan": "k_force_sym_paper", "fp64": "k_force_f64<1>"}
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "force_counters.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2303_12166_amd", "csrc", "nb_kernels.hip")
 
@@ -78,26 +79,33 @@ def cpu_model() -> str:
     return platform.processor()
 
 
-def cpu_baseline(ic, target_seconds: float):
+def cpu_baseline(ic, target_seconds: float, law=None):
     """The FP64 oracle on a bounded row sample of the same workload (one force evaluation)."""
     import numpy as np
 
     import oracle
 
-    p, _ = ic.f32_as_f64()
+    p, v = ic.f32_as_f64()
+    if law is None:
+        def accel(rows):
+            return oracle.accel(p, ic.n1, ic.G, ic.m, ic.D1, ic.D2, rows=rows)
+    else:
+        def accel(rows):
+            return oracle.accel_paper(p, v, ic.n1, ic.G, ic.m, ic.D1, ic.D2, law["eps"],
+                                      law["gamma"], law["beta"], rows=rows)
     n = ic.n
     cores = oracle.max_threads()
     # calibrate on a short sample (second pass: threads already running)
     cal_rows = np.linspace(0, n - 1, 4 * cores).astype(np.int64)
     for _ in range(2):
         t0 = time.perf_counter()
-        oracle.accel(p, ic.n1, ic.G, ic.m, ic.D1, ic.D2, rows=cal_rows)
+        accel(cal_rows)
         t_cal = max(time.perf_counter() - t0, 1e-6)
     rate = len(cal_rows) * n / t_cal
     k = int(min(n, max(64, target_seconds * rate / n)))
     rows = np.linspace(0, n - 1, k).astype(np.int64)
     t0 = time.perf_counter()
-    ref = oracle.accel(p, ic.n1, ic.G, ic.m, ic.D1, ic.D2, rows=rows)
+    ref = accel(rows)
     t = time.perf_counter() - t0
     return {
         "value": k * n / t,
@@ -107,7 +115,45 @@ def cpu_baseline(ic, target_seconds: float):
         "sample": "%d of %d rows, each against all %d elements (one FP64 force evaluation "
                   "of the step-0 state, %.1f s)" % (k, n, n, t),
         "cpu": cpu_model(),
+        "detail": oracle_scaling(cores) if law is None else None,
     }, rows, ref
+
+
+def oracle_scaling(cores: int) -> dict:
+    """The oracle's force-evaluation rate at the other workload sizes (row samples of about a
+    second each; every row at N = 2048), the whole N = 2048, 100-step run, and one core."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    out = {"interactions_per_s": {}}
+    for n, q in ((2048, 0.5), (65536, 0.5), (131072, 0.8)):
+        ic = synth.make_binary(n, q, seed=0)
+        p, _ = ic.f32_as_f64()
+        k = n if n <= 2048 else max(4 * cores, int(1.0e9 / n))
+        rows = np.linspace(0, n - 1, k).astype(np.int64)
+        oracle.accel(p, ic.n1, ic.G, ic.m, ic.D1, ic.D2, rows=rows[: 4 * cores])
+        t0 = time.perf_counter()
+        oracle.accel(p, ic.n1, ic.G, ic.m, ic.D1, ic.D2, rows=rows)
+        out["interactions_per_s"][str(n)] = k * n / (time.perf_counter() - t0)
+    ic = synth.make_binary(2048, 0.5, seed=0)
+    p, v = ic.f32_as_f64()
+    run = oracle.Run(p, v, ic.n1, ic.G, ic.m, 1e-4, ic.D1, ic.D2, ic.q, a=ic.a, R2_0=ic.R2)
+    t0 = time.perf_counter()
+    run.advance(100)
+    out["n2048_100_step_run_s"] = time.perf_counter() - t0
+    ic = synth.make_binary(65536, 0.5, seed=0)
+    p, _ = ic.f32_as_f64()
+    rows = np.linspace(0, ic.n - 1, 2048).astype(np.int64)
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.accel(p, ic.n1, ic.G, ic.m, ic.D1, ic.D2, rows=rows)
+        out["one_core_interactions_per_s"] = len(rows) * ic.n / (time.perf_counter() - t0)
+    finally:
+        oracle.set_threads(cores)
+    return out
 
 
 def copy_calibration() -> int:
@@ -207,6 +253,66 @@ def precision_study(steps: int) -> dict:
     return out
 
 
+def lobe_fill(extra_steps: int, n: int = 65536, q: float = 0.5, bin_steps: int = 100) -> dict:
+    """Grow the donor to its Roche lobe and past the stop; record the per-step L1 flux series
+    and, every 500 steps, the accretor-side retention of the transferred elements."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import paper_2303_12166_amd as nb
+    import synth
+
+    ic = synth.make_binary(n, q, seed=0)
+    s = nb.System.from_ic(ic, mode="kahan")
+    rows, ret = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, stop_seen = 0, None
+    while stop_seen is None or done < stop_seen + extra_steps:
+        k = 500 if stop_seen is None else min(500, stop_seen + extra_steps - done)
+        s.step(k)
+        done += k
+        rows.append(s.l1_log(k))
+        ret.append({"step": done, "n_past_bound": list(s.retention())})
+        d = s.diagnostics()
+        if stop_seen is None and d["growth_stopped"]:
+            stop_seen = done
+        log("lobe fill: %d steps, past L1 %d, growth %s" % (done, rows[-1][-1, 1],
+                                                          "stopped" if d["growth_stopped"] else "on"))
+        if stop_seen is None and done >= 40000:
+            break
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    d = s.diagnostics()
+    s.close()
+    series = np.concatenate(rows)
+    assert list(series[:, 0]) == list(range(1, done + 1))
+    bins = []
+    for b in range(0, done, bin_steps):
+        seg = series[b:b + bin_steps]
+        bins.append([int(seg[-1, 0]), int(seg[:, 2].sum()), int(seg[:, 3].sum()), int(seg[-1, 1])])
+    first_fwd = np.flatnonzero(series[:, 2] > 0)
+    return {
+        "workload": "two-star binary, N=%d, q=%g, FP32 Kahan, dt=1e-4, donor element diameter "
+                    "grown by 1e-4 per step from R2_0 = %.2f until the nominal radius passes "
+                    "r_L a (eq. 3), then %d more steps" % (n, q, ic.R2, extra_steps),
+        "steps": done,
+        "growth_stopped": d["growth_stopped"],
+        "growth_steps": int(round(math.log(d["D2"] / ic.D2) / math.log(1.0 + 1e-4))),
+        "R2_final": d["R2"],
+        "first_forward_crossing_step": int(series[first_fwd[0], 0]) if first_fwd.size else None,
+        "forward_crossings": int(series[:, 2].sum()),
+        "backward_crossings": int(series[:, 3].sum()),
+        "past_L1_at_end": int(series[-1, 1]),
+        "bins": {"columns": ["last_step", "forward", "backward", "past_L1_at_end"],
+                 "rows": bins},
+        "retention": ret,
+        "ms_per_step": t / done * 1e3,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -214,6 +320,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="c3")
     ap.add_argument("--mode", choices=["kahan", "plain", "fp64"], default=None)
+    ap.add_argument("--law", choices=["contact", "paper"], default="contact",
+                    help="element law: the conservative contact law (default) or the paper's "
+                         "eqs. (4)-(6) (velocity-noised start, gamma/eps/beta from "
+                         "synth.paper_law_params; Kahan or FP64 only)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--serve", choices=["none", "small", "full"], default="small",
@@ -223,6 +333,10 @@ def main() -> int:
                     help="N=131072, q=0.8: FP32 plain, FP32 Kahan and FP64 runs of --steps steps "
                          "(default 2000), step-0 force error vs the FP64 oracle and FP64 drift of "
                          "E, P and L (donor growth off so that the energy is conserved)")
+    ap.add_argument("--lobe-fill", action="store_true",
+                    help="N=65536, q=0.5: grow the donor to its Roche lobe (about 4150 steps) and "
+                         "run --steps more after growth stops (default 2000); prints the binned "
+                         "L1 flux series and the accretor-side retention")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (three times), the reference "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -239,6 +353,18 @@ def main() -> int:
         res = precision_study(args.steps or 2000)
         print(json.dumps({"metric": "precision study (force error, E/P/L drift)", "value": None,
                           "n_gpus": 1, "data": "synthetic", "precision_study": res}), flush=True)
+        return 0
+    if args.lobe_fill:
+        import torch
+
+        import paper_2303_12166_amd as nb
+
+        nb.load()
+        torch.cuda.set_device(0)
+        res = lobe_fill(2000 if args.steps is None else args.steps)
+        print(json.dumps({"metric": "lobe-filling run: L1 flux series and retention",
+                          "value": None, "n_gpus": 1, "data": "synthetic", "lobe_fill": res}),
+              flush=True)
         return 0
     if args.serve == "full":
         import torch
@@ -281,7 +407,14 @@ def main() -> int:
     log("workload %s: N=%d q=%.2f mode=%s steps=%d warmup=%d" % (args.workload, n, q, mode, steps,
                                                                   warmup))
     ic = synth.make_binary(n, q, seed=0)
-    s = nb.System.from_ic(ic, mode=mode, dt=1e-4)
+    law = None
+    if args.law == "paper":
+        if mode == "plain":
+            print("the paper's law has no plain FP32 kernel", file=sys.stderr)
+            return 2
+        ic = synth.with_velocity_noise(ic, 0.05, 1000)
+        law = synth.paper_law_params(ic)
+    s = nb.System.from_ic(ic, mode=mode, dt=1e-4, **(law or {}))
     a0 = s.accelerations()
     cfg = nb.nb_tile_config(n, ic.n1, nb.MODES[mode])
     log("tile config", cfg)
@@ -314,8 +447,9 @@ def main() -> int:
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4),
-        "traffic": hbm_traffic(args.workload, mode),
-        "kernel": KERNEL_NAMES[mode],
+        "traffic": hbm_traffic(args.workload + (":paper" if law else ""), mode),
+        "kernel": (PAPER_KERNEL_NAMES if law else KERNEL_NAMES)[mode],
+        "flops_per_interaction": FLOPS_PER_INTERACTION,
         "avg_launch_ms": round(avg_s * 1e3, 4),
         "launches": launches,
         "flops_per_launch": FLOPS_PER_INTERACTION * inter,
@@ -336,12 +470,14 @@ def main() -> int:
         "dtype": "f64" if mode == "fp64" else "f32",
         "data": "synthetic",
         "config": {
-            "workload": "two-star binary, N=%d, q=%g, %s forces, dt=1e-4, donor growth + L1 "
+            "workload": "two-star binary, N=%d, q=%g, %s forces%s, dt=1e-4, donor growth + L1 "
                         "count every step" % (n, q, {"kahan": "FP32 Kahan", "plain": "FP32 plain",
-                                                       "fp64": "FP64"}[mode]),
+                                                       "fp64": "FP64"}[mode],
+                                              " under eqs. (4)-(6)" if law else ""),
             "n": n,
             "q": q,
             "mode": mode,
+            "law": args.law,
             "seed": 0,
             "tile": cfg,
         },
@@ -352,7 +488,7 @@ def main() -> int:
     s.close()
 
     if not args.no_cpu:
-        base, rows, ref = cpu_baseline(ic, args.cpu_seconds)
+        base, rows, ref = cpu_baseline(ic, args.cpu_seconds, law)
         out["cpu_baseline"] = base
         err = (np.linalg.norm(a0[rows] - ref, axis=1).max() / np.linalg.norm(ref, axis=1).max())
         out["force_error_step0"] = {"value": float(err), "rows": int(len(rows)),

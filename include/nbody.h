@@ -47,6 +47,11 @@ extern "C" {
 #define NB_E_NONFINITE (-4) /* a position or velocity became NaN or infinite */
 #define NB_E_MISMATCH (-5)  /* systems of different precision modes in one multi-system call */
 
+/* element laws */
+#define NB_LAW_CONTACT 0 /* conservative contact law (default; see the header comment) */
+#define NB_LAW_PAPER 1   /* eqs. (4)-(6): G m^2/(r+eps)^2 minus gamma V(r) in contact, times beta
+                            while the pair does not converge (FP32 Kahan and FP64 modes only) */
+
 /* precision modes of the force evaluation */
 #define NB_FP32_PLAIN 0 /* FP32, one running sum per element over all j in order */
 #define NB_FP32_KAHAN 1 /* FP32 tile partials, compensated (Kahan) sum across tiles */
@@ -69,6 +74,16 @@ typedef struct {
     double growth_rate;  /* D2 <- D2 (1 + growth_rate) per step while growing */
     int32_t growth_on;   /* 0: the donor never grows */
     int32_t mode;        /* NB_FP32_PLAIN, NB_FP32_KAHAN or NB_FP64 */
+    int32_t law;         /* NB_LAW_CONTACT or NB_LAW_PAPER */
+    int32_t pad;
+    /* NB_LAW_PAPER only (eqs. 4-6). Pair radius R = D_ij / 2; contact means r < 2R; V(r) =
+     * pi (4/3 R^3 - R^2 r + r^3/12) is the overlap volume of two spheres of radius R; the pair
+     * converges when (v_j - v_i).(r_j - r_i) < 0, and the force law then reads
+     *   f(r) = G m^2 / (r + eps)^2 - g V(r),  g = gamma (converging) or gamma beta (otherwise).
+     * The force seen in a leap-frog step uses the half-step velocities. Requires G > 0. */
+    double eps;          /* softening length (>= 0) */
+    double gamma;        /* repulsion per unit overlap volume (>= 0) */
+    double beta;         /* reduction factor while not converging (0 <= beta <= 1) */
 } nb_params;
 
 /* Device buffers of one system (caller-owned, see the conventions above). */
@@ -148,6 +163,15 @@ int nb_diagnostics(nb_system *s, int32_t with_pe, nb_diag *out, void *stream);
  * keeps the last NB_L1_LOG_CAP steps. Synchronises `stream`. *n_out receives the row count. */
 #define NB_L1_LOG_CAP 4096
 int nb_l1_log(nb_system *s, int32_t *out_host, int32_t max_steps, int32_t *n_out, void *stream);
+
+/* Accretor-side retention of the mass that crossed L1 (Methodology: transfer through L1 onto the
+ * accretor; eq. 2's geometry). Of the donor elements past the L1 plane of the current state (the
+ * plane the last step used), *n_past is their count and *n_bound those bound to the accretor
+ * taken as a point mass n1 m at its centre of mass C1, moving with star 1's mean velocity V1:
+ * |v - V1|^2 / 2 - G n1 m / |r - C1| < 0. Evaluated in FP64 from the current state (FP32 state
+ * promoted in the FP32 modes). Both are 0 when either star is empty. Synchronises `stream`.
+ * Returns NB_E_INVAL for null arguments. */
+int nb_retention(nb_system *s, int32_t *n_past, int32_t *n_bound, void *stream);
 
 /* Force-kernel timing: while enabled, every force launch issued by nb_forces/nb_step is
  * bracketed by HIP events on its stream. nb_timing_read synchronises those events and returns

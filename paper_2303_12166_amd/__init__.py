@@ -17,7 +17,10 @@ import numpy as np
 
 from . import _abi
 from ._abi import (  # noqa: F401
+    LAWS,
     MODES,
+    NB_LAW_CONTACT,
+    NB_LAW_PAPER,
     NB_E_HIP,
     NB_E_INVAL,
     NB_E_MISMATCH,
@@ -146,6 +149,14 @@ def nb_diagnostics(handle: ctypes.c_void_p, with_pe: bool = False, stream=None) 
         "nonfinite": int(d.nonfinite),
         "status": int(rc),
     }
+
+
+def nb_retention(handle: ctypes.c_void_p, stream=None) -> tuple:
+    """(n_past, n_bound): donor elements past L1 and those of them bound to the accretor."""
+    past, bound = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(load().nb_retention(handle, ctypes.byref(past), ctypes.byref(bound), _stream(stream)),
+           "nb_retention")
+    return int(past.value), int(bound.value)
 
 
 def nb_l1_log(handle: ctypes.c_void_p, max_steps: int = NB_L1_LOG_CAP, stream=None) -> np.ndarray:

@@ -21,6 +21,9 @@ NB_FP64 = 2
 NB_L1_LOG_CAP = 4096
 
 MODES = {"plain": NB_FP32_PLAIN, "kahan": NB_FP32_KAHAN, "fp64": NB_FP64}
+NB_LAW_CONTACT = 0
+NB_LAW_PAPER = 1
+LAWS = {"contact": NB_LAW_CONTACT, "paper": NB_LAW_PAPER}
 
 EXPORTED = (
     "nb_scratch_bytes",
@@ -29,6 +32,7 @@ EXPORTED = (
     "nb_step",
     "nb_diagnostics",
     "nb_l1_log",
+    "nb_retention",
     "nb_timing_enable",
     "nb_timing_read",
     "nb_timing_reset",
@@ -59,6 +63,11 @@ class NbParams(ctypes.Structure):
         ("growth_rate", ctypes.c_double),
         ("growth_on", ctypes.c_int32),
         ("mode", ctypes.c_int32),
+        ("law", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+        ("eps", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("beta", ctypes.c_double),
     ]
 
 
@@ -102,6 +111,7 @@ def declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.nb_step.argtypes = [P(_vp), _i32, _i32, _vp]
     lib.nb_diagnostics.argtypes = [_vp, _i32, P(NbDiag), _vp]
     lib.nb_l1_log.argtypes = [_vp, P(_i32), _i32, P(_i32), _vp]
+    lib.nb_retention.argtypes = [_vp, P(_i32), P(_i32), _vp]
     lib.nb_timing_enable.argtypes = [_i32]
     lib.nb_timing_read.argtypes = [P(ctypes.c_double), P(_i64)]
     lib.nb_timing_reset.argtypes = []

@@ -20,8 +20,17 @@ namespace nbk {
 #ifndef NB_SYM_UNROLL
 #define NB_SYM_UNROLL 1    // groups of four j per unrolled step of the symmetric kernel
 #endif
+#ifndef NB_SYM_DUP
+#define NB_SYM_DUP 0       // 1: each 64-element LDS group stored twice (no wrap on rotation)
+#endif
+#ifndef NB_COMBINE_SEGS
+#define NB_COMBINE_SEGS 1  // threads per element in the symmetric combine (1, 2 or 4)
+#endif
 #ifndef NB_SYM_WAVES_PER_EU
 #define NB_SYM_WAVES_PER_EU 6
+#endif
+#ifndef NB_SYM_PAPER_WAVES_PER_EU
+#define NB_SYM_PAPER_WAVES_PER_EU 5  // eqs. (4)-(6) variant: more live values per pair
 #endif
 #if NB_WAVES_PER_EU > 0
 #define NB_FORCE_ATTR __attribute__((amdgpu_waves_per_eu(NB_WAVES_PER_EU)))
@@ -33,6 +42,11 @@ namespace nbk {
 #else
 #define NB_SYM_ATTR
 #endif
+#if NB_SYM_PAPER_WAVES_PER_EU > 0
+#define NB_SYM_PAPER_ATTR __attribute__((amdgpu_waves_per_eu(NB_SYM_PAPER_WAVES_PER_EU)))
+#else
+#define NB_SYM_PAPER_ATTR
+#endif
 
 constexpr int BT = 256;          // threads per block, every kernel
 constexpr int TJ = 256;          // j elements staged in LDS per tile (one per thread)
@@ -41,6 +55,7 @@ constexpr int KI64 = 1;          // i elements per lane, FP64 force kernel
 constexpr int RED_STRIDE = 32;   // doubles per O(N)-unit partial record
 constexpr int RED_STEP = 0;      // record slots [0, 16): per-step sums (COMs, flags, L1 counts)
 constexpr int RED_DIAG = 16;     // record slots [16, 32): diagnostics sums
+constexpr int RED_RET = 26;      // record slots [26, 31): retention sums (after the diagnostics)
 constexpr int L1_LOG_CAP = 4096; // rows of the per-step L1 log
 // Position of padding slots in the sorted layout. A padding element at 1e18 (FP32) or 1e150
 // (FP64) gives w^3 below the type's smallest subnormal, so its contribution is exactly 0.
@@ -66,7 +81,16 @@ struct alignas(16) DevState {
     int64_t step;
     int32_t growth_on, growth_stopped;
     int32_t n_past, fwd, bwd, nonfinite;
-    int32_t plane_ok, pad_i;
+    int32_t plane_ok, law;
+    // element law of eqs. (4)-(6), with the overlap volume written as (pi / 12) (D - r)^2
+    // (r + 2D), D = 2R the pair's element diameter: gc = gamma pi / (12 G m^2) and
+    // gcb = beta gc scale it for converging and separating pairs; eps softens the attraction
+    double gamma, beta, leps_d, lgc_d, lgcb_d;
+    float lD_f[3];           // D per pair class (follows the donor growth)
+    float leps_f, lgc_f, lgcb_f, pad_l;
+    // accretor-side retention (nb_retention): star 1's mean velocity and the two counts
+    double v1[3];
+    int32_t ret_past, ret_bound;
 };
 
 struct DiagOut {
@@ -104,6 +128,8 @@ struct SysDesc {
     int32_t *units;       // n_units pairs (I, c)
     float *react;         // 3 * TJ * ntiles (ntiles - 1) / 2 reaction sums
     int32_t ch, sym;      // tiles per chunk; 1 when the symmetric kernel is used
+    void *vxs, *vys, *vzs;  // sorted velocities (eqs. 4-6 only; null otherwise)
+    int32_t law, pad3;
 };
 
 // Kernel argument describing one launch over a segment table.
@@ -113,11 +139,13 @@ struct Launch {
     int32_t total_units;   // force units: (i-block, j chunk) pairs
     int32_t total_ounits;  // O(N) units: 256 elements in element order
     int32_t total_tunits;  // tiles: 256 slots in sorted order
+    int32_t law;           // element law of every system in the launch (NB_LAW_*)
 };
 
 // Host-side launchers (nb_kernels.hip). All return the HIP status of the launch.
 hipError_t launch_init_state(DevState *st, const DevState &init, hipStream_t s);
-hipError_t launch_fill_sorted(void *xs, void *ys, void *zs, int nalloc, int mode, hipStream_t s);
+hipError_t launch_fill_sorted(void *xs, void *ys, void *zs, int nalloc, int mode, bool sentinel,
+                              hipStream_t s);
 hipError_t launch_gather(const Launch &L, int mode, hipStream_t s);
 hipError_t launch_forces(const Launch &L, int mode, int max_blocks, hipStream_t s);
 hipError_t launch_combine(const Launch &L, int mode, hipStream_t s);
@@ -127,5 +155,6 @@ hipError_t launch_finalize_step(const Launch &L, int do_growth, hipStream_t s);
 hipError_t launch_l1_classify(const Launch &L, int mode, int init, hipStream_t s);
 hipError_t launch_finalize_l1(const Launch &L, int init, hipStream_t s);
 hipError_t launch_diag(const Launch &L, int mode, int with_pe, hipStream_t s);
+hipError_t launch_retention(const Launch &L, int mode, hipStream_t s);
 
 }  // namespace nbk

@@ -82,6 +82,8 @@ __device__ __forceinline__ void kahan_add(float &sum, float &comp, float v)
 
 __device__ __forceinline__ int pair_class(int istar, int jstar) { return istar + jstar; }
 
+constexpr double PI_D = 3.14159265358979323846;
+
 // ------------------------------------------------------------------ sorted layout
 
 __device__ __forceinline__ int find_tile_sys(const Launch &L, int u)
@@ -113,18 +115,18 @@ __device__ __forceinline__ float wave_max(float v)
 }
 
 template <typename T>
-__global__ __launch_bounds__(BT) void k_fill_sorted(T *xs, T *ys, T *zs, int nalloc, T sentinel)
+__global__ __launch_bounds__(BT) void k_fill_sorted(T *xs, T *ys, T *zs, int nalloc, T value)
 {
     const int k = blockIdx.x * BT + threadIdx.x;
     if (k < nalloc) {
-        xs[k] = sentinel;
-        ys[k] = sentinel;
-        zs[k] = sentinel;
+        xs[k] = value;
+        ys[k] = value;
+        zs[k] = value;
     }
 }
 
-// Pulls the current positions into sorted order and records each tile's bounding box (padding
-// slots keep their sentinel and are left out of the box).
+// Pulls the current positions (and, under eqs. (4)-(6), velocities) into sorted order and records
+// each tile's bounding box (padding slots keep their fill values and are left out of the box).
 template <typename T>
 __global__ __launch_bounds__(BT) void k_gather(Launch L)
 {
@@ -143,6 +145,11 @@ __global__ __launch_bounds__(BT) void k_gather(Launch L)
             static_cast<T *>(S.xs)[slot] = x;
             static_cast<T *>(S.ys)[slot] = y;
             static_cast<T *>(S.zs)[slot] = z;
+            if (S.vxs) {
+                static_cast<T *>(S.vxs)[slot] = static_cast<const T *>(S.vx)[idx];
+                static_cast<T *>(S.vys)[slot] = static_cast<const T *>(S.vy)[idx];
+                static_cast<T *>(S.vzs)[slot] = static_cast<const T *>(S.vz)[idx];
+            }
             v[0] = v[3] = (float)x;
             v[1] = v[4] = (float)y;
             v[2] = v[5] = (float)z;
@@ -403,35 +410,88 @@ __global__ __launch_bounds__(BT) NB_FORCE_ATTR void k_force_f32(Launch L)
 
 constexpr int DPP_WAVE_ROR1 = 0x13C;  // lane l receives lane l - 1 (mod 64)
 
+// LDS tile layout. With NB_SYM_DUP each group of 64 is stored twice in a row (128 entries), so
+// the rotating read of element (l - s) mod 64 becomes entry l + 64 - s with no wrap-around and
+// the per-step address is one subtraction.
+constexpr int SYM_GSTRIDE = NB_SYM_DUP ? 128 : 64;
+constexpr int SYM_TILE = 4 * SYM_GSTRIDE;
+
+__device__ __forceinline__ int sym_slot(int jj) { return (jj >> 6) * SYM_GSTRIDE + (jj & 63); }
+
 __device__ __forceinline__ float wave_ror1(float v)
 {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), DPP_WAVE_ROR1, 0xf, 0xf, true));
 }
 
-// One-sided diagonal tile from an AoS LDS tile (x, y, z, unused).
-__device__ __forceinline__ void diag_tile(const float4 *__restrict__ sj, IState<1> &I, float c1,
-                                          float nc2)
+// Constants of one pair class for the FP32 kernels.
+struct LawF {
+    float c1, nc2;            // contact law: 11 / D^3 and -10 / D^2
+    float D, twoD, eps, gc, gcb;  // eqs. (4)-(6): see DevState
+};
+
+// Pair scalar s = f / (G m^2 r) of one pair; the caller adds s d to the i sum.
+//   contact law:  min(w^3, c1 - c2 w) near, w^3 far.
+//   eqs. (4)-(6): w / (r + eps)^2 - g (D - r)_+^2 (1 + 2 D w), g = gc for a converging pair
+//                 ((v_j - v_i).(r_j - r_i) < 0) and gcb otherwise; the overlap term is left out
+//                 on far tiles, where every pair has r >= D. (pi / 12) (D - r)^2 (r + 2D) is the
+//                 overlap volume of eq. (5) in factored form, so it has no cancellation near D.
+template <int LAW, bool NEAR>
+__device__ __forceinline__ float pair_s(float r2, float w, float dx, float dy, float dz,
+                                        const float4 &vj, const float4 &vi, const LawF &K)
+{
+#pragma clang fp contract(off)
+    if constexpr (LAW == 0) {
+        const float w3 = (w * w) * w;
+        return NEAR ? fminf(w3, fmaf(K.nc2, w, K.c1)) : w3;
+    } else {
+        const float r = r2 * w;
+        const float it = __builtin_amdgcn_rcpf(r + K.eps);
+        float s = (it * it) * w;
+        if constexpr (NEAR) {
+            const float dot = fmaf(vj.x - vi.x, dx, fmaf(vj.y - vi.y, dy, (vj.z - vi.z) * dz));
+            const float g = dot < 0.0f ? K.gc : K.gcb;
+            const float u = fmaxf(K.D - r, 0.0f);
+            s = s - ((g * u) * u) * fmaf(K.twoD, w, 1.0f);
+        }
+        return s;
+    }
+}
+
+// One-sided diagonal tile from an AoS LDS tile (x, y, z, unused). The self pair has d = 0; under
+// eqs. (4)-(6) it is also masked, since its overlap term is of order 1/eps.
+template <int LAW>
+__device__ __forceinline__ void diag_tile(const float4 *__restrict__ sj,
+                                          const float4 *__restrict__ sv, IState<1> &I,
+                                          const float4 &vi, const LawF &K)
 {
     const float eps = 1.0e-24f;
+    const int self = threadIdx.x;
 #pragma unroll 4
     for (int jj = 0; jj < TJ; ++jj) {
-        const float4 P = sj[jj];
+        const float4 P = sj[sym_slot(jj)];
         const float dx = P.x - I.x[0];
         const float dy = P.y - I.y[0];
         const float dz = P.z - I.z[0];
         const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
         const float w = __builtin_amdgcn_rsqf(r2);
-        const float w3 = (w * w) * w;
-        const float s = fminf(w3, fmaf(nc2, w, c1));
+        float s;
+        if constexpr (LAW == 0) {
+            s = pair_s<0, true>(r2, w, dx, dy, dz, vi, vi, K);
+        } else {
+            s = pair_s<LAW, true>(r2, w, dx, dy, dz, sv[sym_slot(jj)], vi, K);
+            s = jj == self ? 0.0f : s;
+        }
         I.ax[0] = fmaf(s, dx, I.ax[0]);
         I.ay[0] = fmaf(s, dy, I.ay[0]);
         I.az[0] = fmaf(s, dz, I.az[0]);
     }
 }
 
-template <bool NEAR>
-__device__ __forceinline__ void sym_tile(const float4 *__restrict__ sj, IState<1> &I, float c1,
-                                         float nc2, float *rwx, float *rwy, float *rwz, int lane)
+template <bool NEAR, int LAW>
+__device__ __forceinline__ void sym_tile(const float4 *__restrict__ sj,
+                                         const float4 *__restrict__ sv, IState<1> &I,
+                                         const float4 &vi, const LawF &K, float *rwx, float *rwy,
+                                         float *rwz, int lane)
 {
     // keep p = s d and the rotated update a_j <- rotate(a_j) - p as separate operations, so that
     // the rotation folds into the subtraction (a VOP2 instruction with a DPP source)
@@ -441,17 +501,21 @@ __device__ __forceinline__ void sym_tile(const float4 *__restrict__ sj, IState<1
     float ajz[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll NB_SYM_UNROLL
     for (int st = 0; st < 64; ++st) {
-        const int e = (lane - st) & 63;
+        const int e = NB_SYM_DUP ? lane + 64 - st : (lane - st) & 63;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-            const float4 P = sj[g * 64 + e];
+            const float4 P = sj[g * SYM_GSTRIDE + e];
             const float dx = P.x - I.x[0];
             const float dy = P.y - I.y[0];
             const float dz = P.z - I.z[0];
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
             const float w = __builtin_amdgcn_rsqf(r2);
-            const float w3 = (w * w) * w;
-            const float s = NEAR ? fminf(w3, fmaf(nc2, w, c1)) : w3;
+            float s;
+            if constexpr (LAW != 0 && NEAR) {
+                s = pair_s<LAW, NEAR>(r2, w, dx, dy, dz, sv[g * SYM_GSTRIDE + e], vi, K);
+            } else {
+                s = pair_s<LAW, NEAR>(r2, w, dx, dy, dz, vi, vi, K);
+            }
             const float px = s * dx, py = s * dy, pz = s * dz;
             I.ax[0] += px;
             I.ay[0] += py;
@@ -470,6 +534,19 @@ __device__ __forceinline__ void sym_tile(const float4 *__restrict__ sj, IState<1
     }
 }
 
+__device__ __forceinline__ LawF law_f(const DevState *st, int cls)
+{
+    LawF K;
+    K.c1 = st->c1f[cls];
+    K.nc2 = -st->c2f[cls];
+    K.D = st->lD_f[cls];
+    K.twoD = 2.0f * st->lD_f[cls];
+    K.eps = st->leps_f;
+    K.gc = st->lgc_f;
+    K.gcb = st->lgcb_f;
+    return K;
+}
+
 // Reactions of row I are stored row after row: row I covers slots [TJ (I + 1), npad), three
 // components one after the other.
 __device__ __forceinline__ size_t react_row_offset(int I, int npad)
@@ -477,12 +554,17 @@ __device__ __forceinline__ size_t react_row_offset(int I, int npad)
     return (size_t)3 * ((size_t)I * npad - (size_t)TJ * I * (I + 1) / 2);
 }
 
-__device__ void force_unit_sym(const SysDesc &S, int I, int c, float4 *sj, float (*rw)[3][TJ])
+template <int LAW>
+__device__ void force_unit_sym(const SysDesc &S, int I, int c, float4 *sj, float4 *sv,
+                               float (*rw)[3][TJ])
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const float *__restrict__ XS = static_cast<const float *>(S.xs);
     const float *__restrict__ YS = static_cast<const float *>(S.ys);
     const float *__restrict__ ZS = static_cast<const float *>(S.zs);
+    const float *__restrict__ VXS = static_cast<const float *>(S.vxs);
+    const float *__restrict__ VYS = static_cast<const float *>(S.vys);
+    const float *__restrict__ VZS = static_cast<const float *>(S.vzs);
     const DevState *st = S.st;
     const int slot = I * TJ + tid;
     IState<1> Ist;
@@ -490,6 +572,8 @@ __device__ void force_unit_sym(const SysDesc &S, int I, int c, float4 *sj, float
     Ist.y[0] = YS[slot];
     Ist.z[0] = ZS[slot];
     Ist.ax[0] = Ist.ay[0] = Ist.az[0] = 0.0f;
+    float4 vi = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (LAW != 0) vi = make_float4(VXS[slot], VYS[slot], VZS[slot], 0.0f);
     const bool real = S.perm[slot] >= 0;
     float lo[3], hi[3];
     lo[0] = wave_min(real ? Ist.x[0] : INFINITY);
@@ -499,8 +583,8 @@ __device__ void force_unit_sym(const SysDesc &S, int I, int c, float4 *sj, float
     hi[1] = wave_max(real ? Ist.y[0] : -INFINITY);
     hi[2] = wave_max(real ? Ist.z[0] : -INFINITY);
     const int istar = I * TJ >= S.p1 ? 1 : 0;
-    const float c1a = st->c1f[istar], nc2a = -st->c2f[istar], far2a = st->far2f[istar];
-    const float c1b = st->c1f[istar + 1], nc2b = -st->c2f[istar + 1], far2b = st->far2f[istar + 1];
+    const LawF Ka = law_f(st, istar), Kb = law_f(st, istar + 1);
+    const float far2a = st->far2f[istar], far2b = st->far2f[istar + 1];
 
     float sumx = 0.f, sumy = 0.f, sumz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
     const int t0 = I + c * S.ch;
@@ -509,24 +593,49 @@ __device__ void force_unit_sym(const SysDesc &S, int I, int c, float4 *sj, float
     float *R = S.react;
     const size_t roff = react_row_offset(I, npad);
     const size_t rlen = (size_t)npad - (size_t)TJ * (I + 1);
-    float px = 0.f, py = 0.f, pz = 0.f;
+    float px = 0.f, py = 0.f, pz = 0.f, qx = 0.f, qy = 0.f, qz = 0.f;
     if (t0 < t1) {
         px = XS[t0 * TJ + tid];
         py = YS[t0 * TJ + tid];
         pz = ZS[t0 * TJ + tid];
+        if constexpr (LAW != 0) {
+            qx = VXS[t0 * TJ + tid];
+            qy = VYS[t0 * TJ + tid];
+            qz = VZS[t0 * TJ + tid];
+        }
     }
     for (int t = t0; t < t1; ++t) {
-        sj[tid] = make_float4(px, py, pz, 0.0f);
+        {
+            const int at = sym_slot(tid);
+            sj[at] = make_float4(px, py, pz, 0.0f);
+            if constexpr (LAW != 0) sv[at] = make_float4(qx, qy, qz, 0.0f);
+            if constexpr (NB_SYM_DUP != 0) {
+                sj[at + 64] = make_float4(px, py, pz, 0.0f);
+                if constexpr (LAW != 0) sv[at + 64] = make_float4(qx, qy, qz, 0.0f);
+            }
+        }
         __syncthreads();
         if (t + 1 < t1) {
             px = XS[(t + 1) * TJ + tid];
             py = YS[(t + 1) * TJ + tid];
             pz = ZS[(t + 1) * TJ + tid];
+            if constexpr (LAW != 0) {
+                qx = VXS[(t + 1) * TJ + tid];
+                qy = VYS[(t + 1) * TJ + tid];
+                qz = VZS[(t + 1) * TJ + tid];
+            }
         }
         const bool jstar = t * TJ >= S.p1;
-        const float c1 = jstar ? c1b : c1a, nc2 = jstar ? nc2b : nc2a;
+        LawF K;
+        K.c1 = jstar ? Kb.c1 : Ka.c1;
+        K.nc2 = jstar ? Kb.nc2 : Ka.nc2;
+        K.D = jstar ? Kb.D : Ka.D;
+        K.twoD = jstar ? Kb.twoD : Ka.twoD;
+        K.eps = Ka.eps;
+        K.gc = Ka.gc;
+        K.gcb = Ka.gcb;
         if (t == I) {
-            diag_tile(sj, Ist, c1, nc2);
+            diag_tile<LAW>(sj, sv, Ist, vi, K);
         } else {
             const float *bx = S.tbox + (size_t)t * 8;
             const float gx = fmaxf(0.0f, fmaxf(bx[0] - hi[0], lo[0] - bx[4]));
@@ -535,9 +644,11 @@ __device__ void force_unit_sym(const SysDesc &S, int I, int c, float4 *sj, float
             const float gap2 = gx * gx + gy * gy + gz * gz;
             const int far = __builtin_amdgcn_readfirstlane(gap2 >= (jstar ? far2b : far2a) ? 1 : 0);
             if (far) {
-                sym_tile<false>(sj, Ist, 0.f, 0.f, rw[wave][0], rw[wave][1], rw[wave][2], lane);
+                sym_tile<false, LAW>(sj, sv, Ist, vi, K, rw[wave][0], rw[wave][1], rw[wave][2],
+                                     lane);
             } else {
-                sym_tile<true>(sj, Ist, c1, nc2, rw[wave][0], rw[wave][1], rw[wave][2], lane);
+                sym_tile<true, LAW>(sj, sv, Ist, vi, K, rw[wave][0], rw[wave][1], rw[wave][2],
+                                    lane);
             }
             __syncthreads();
             const size_t at = roff + (size_t)t * TJ + tid - (size_t)TJ * (I + 1);
@@ -550,7 +661,7 @@ __device__ void force_unit_sym(const SysDesc &S, int I, int c, float4 *sj, float
         kahan_add(sumy, cy, Ist.ay[0]);
         kahan_add(sumz, cz, Ist.az[0]);
         Ist.ax[0] = Ist.ay[0] = Ist.az[0] = 0.0f;
-        __syncthreads();  // sj and rw are rewritten by the next tile
+        __syncthreads();  // sj, sv and rw are rewritten by the next tile
     }
     if (real) {
         float *P = static_cast<float *>(S.part);
@@ -564,61 +675,99 @@ __device__ void force_unit_sym(const SysDesc &S, int I, int c, float4 *sj, float
 
 __global__ __launch_bounds__(BT) NB_SYM_ATTR void k_force_sym(Launch L)
 {
-    __shared__ float4 sj[TJ];
+    __shared__ float4 sj[SYM_TILE];
     __shared__ __attribute__((aligned(16))) float rw[BT / 64][3][TJ];
     for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
         const SysDesc &S = L.sys[find_sys(L, u, false)];
         const int2 ic = reinterpret_cast<const int2 *>(S.units)[u - S.unit_begin];
-        force_unit_sym(S, ic.x, ic.y, sj, rw);
+        force_unit_sym<0>(S, ic.x, ic.y, sj, nullptr, rw);
     }
 }
 
-// a = G m (sum of the row's chunk partials, then the reactions of rows 0 .. J-1), in that order
-// with Kahan compensation, scattered to the element's own index.
-__global__ __launch_bounds__(BT) void k_combine_sym(Launch L)
+// The same under eqs. (4)-(6): each tile also stages the sorted half-step velocities.
+__global__ __launch_bounds__(BT) NB_SYM_PAPER_ATTR void k_force_sym_paper(Launch L)
 {
+    __shared__ float4 sj[SYM_TILE];
+    __shared__ float4 sv[SYM_TILE];
+    __shared__ __attribute__((aligned(16))) float rw[BT / 64][3][TJ];
+    for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
+        const SysDesc &S = L.sys[find_sys(L, u, false)];
+        const int2 ic = reinterpret_cast<const int2 *>(S.units)[u - S.unit_begin];
+        force_unit_sym<1>(S, ic.x, ic.y, sj, sv, rw);
+    }
+}
+
+// a = G m (sum of the row's chunk partials, then the reactions of rows 0 .. J-1), scattered to
+// the element's own index. Each element's rows are cut into SEGS contiguous runs, summed by SEGS
+// threads at once (more loads in flight for the long rows of the last tiles); each run is a
+// Kahan sum in row order (the first run starts with the chunk partials), and the run results are
+// added in run order with Kahan compensation. The order is fixed, so the result is too.
+template <int SEGS>
+__global__ __launch_bounds__(BT * SEGS) void k_combine_sym(Launch L)
+{
+    __shared__ float part[SEGS > 1 ? SEGS : 1][3][BT];
+    const int e = threadIdx.x % BT, k = threadIdx.x / BT;
     for (int u = blockIdx.x; u < L.total_tunits; u += gridDim.x) {
         const SysDesc &S = L.sys[find_tile_sys(L, u)];
         const int J = u - S.tunit_begin;
-        const int slot = J * TJ + threadIdx.x;
+        const int slot = J * TJ + e;
         const int idx = S.perm[slot];
-        if (idx < 0) continue;
         const float *P = static_cast<const float *>(S.part);
         const float *R = S.react;
         const size_t na = S.nalloc;
         const int npad = S.npad;
         const int cj = (S.ntiles - J + S.ch - 1) / S.ch;
-        float out[3];
-        for (int d = 0; d < 3; ++d) {
-            float sum = 0.f, comp = 0.f;
-            for (int c = 0; c < cj; ++c) kahan_add(sum, comp, P[(size_t)c * 3 * na + d * na + slot]);
-            // rows are read eight at a time (independent loads in flight), then added in row
-            // order; the arithmetic is the same as one row at a time
-            size_t off = 0;
-            size_t len = (size_t)npad - TJ;
-            int I = 0;
-            for (; I + 8 <= J; I += 8) {
-                float v[8];
+        const int r0 = (int)(((int64_t)J * k) / SEGS), r1 = (int)(((int64_t)J * (k + 1)) / SEGS);
+        float out[3] = {0.f, 0.f, 0.f};
+        if (idx >= 0) {
+            for (int d = 0; d < 3; ++d) {
+                float sum = 0.f, comp = 0.f;
+                if (k == 0) {
+                    for (int c = 0; c < cj; ++c)
+                        kahan_add(sum, comp, P[(size_t)c * 3 * na + d * na + slot]);
+                }
+                // rows are read eight at a time (independent loads in flight), then added in
+                // row order; the arithmetic is the same as one row at a time
+                size_t off = react_row_offset(r0, npad);
+                size_t len = (size_t)npad - (size_t)TJ * (r0 + 1);
+                int I = r0;
+                for (; I + 8 <= r1; I += 8) {
+                    float v[8];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    v[k] = R[off + d * len + slot - (size_t)TJ * (I + k + 1)];
+                    for (int q = 0; q < 8; ++q) {
+                        v[q] = R[off + d * len + slot - (size_t)TJ * (I + q + 1)];
+                        off += 3 * len;
+                        len -= TJ;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) kahan_add(sum, comp, v[q]);
+                }
+                for (; I < r1; ++I) {
+                    kahan_add(sum, comp, R[off + d * len + slot - (size_t)TJ * (I + 1)]);
                     off += 3 * len;
                     len -= TJ;
                 }
-#pragma unroll
-                for (int k = 0; k < 8; ++k) kahan_add(sum, comp, v[k]);
+                out[d] = sum - comp;
             }
-            for (; I < J; ++I) {
-                kahan_add(sum, comp, R[off + d * len + slot - (size_t)TJ * (I + 1)]);
-                off += 3 * len;
-                len -= TJ;
-            }
-            out[d] = sum - comp;
         }
-        const float gm = S.st->gm_f;
-        static_cast<float *>(S.ax)[idx] = gm * out[0];
-        static_cast<float *>(S.ay)[idx] = gm * out[1];
-        static_cast<float *>(S.az)[idx] = gm * out[2];
+        if constexpr (SEGS > 1) {
+            for (int d = 0; d < 3; ++d) part[k][d][e] = out[d];
+            __syncthreads();
+            if (k == 0 && idx >= 0) {
+                for (int d = 0; d < 3; ++d) {
+                    float sum = out[d], comp = 0.f;
+                    for (int q = 1; q < SEGS; ++q) kahan_add(sum, comp, part[q][d][e]);
+                    out[d] = sum - comp;
+                }
+            }
+            __syncthreads();
+        }
+        if (k == 0 && idx >= 0) {
+            const float gm = S.st->gm_f;
+            static_cast<float *>(S.ax)[idx] = gm * out[0];
+            static_cast<float *>(S.ay)[idx] = gm * out[1];
+            static_cast<float *>(S.az)[idx] = gm * out[2];
+        }
     }
 }
 
@@ -634,15 +783,50 @@ __device__ __forceinline__ double rsqrt_f64(double r2)
     return y;
 }
 
+// Pair scalar s = f / (G m^2 r) in FP64 (see pair_s); D is the pair's element diameter and
+// w = 1 / r (0 for coincident elements, whose d = 0).
+template <int LAW>
+__device__ __forceinline__ double pair_s64(double r2, double w, double dx, double dy, double dz,
+                                           double dvx, double dvy, double dvz, double D,
+                                           double c1, double c2, const DevState *st)
+{
+    if constexpr (LAW == 0) {
+        const double w3 = w * w * w;
+        return fmin(w3, c1 - c2 * w);
+    } else {
+        if (!(r2 > 0.0)) return 0.0;
+        const double r = r2 * w;
+        const double t = r + st->leps_d;
+        double s = w / (t * t);
+        if (r < D) {
+            const double dot = dvx * dx + dvy * dy + dvz * dz;
+            const double g = dot < 0.0 ? st->lgc_d : st->lgcb_d;
+            const double u = D - r;
+            s -= g * u * u * (1.0 + 2.0 * D * w);
+        }
+        return s;
+    }
+}
+
+template <int LAW>
 __device__ void force_unit_f64(const SysDesc &S, int ib, int c, double (*sh)[TJ])
 {
     const int tid = threadIdx.x;
     const double *__restrict__ XS = static_cast<const double *>(S.xs);
     const double *__restrict__ YS = static_cast<const double *>(S.ys);
     const double *__restrict__ ZS = static_cast<const double *>(S.zs);
+    const double *__restrict__ VXS = static_cast<const double *>(S.vxs);
+    const double *__restrict__ VYS = static_cast<const double *>(S.vys);
+    const double *__restrict__ VZS = static_cast<const double *>(S.vzs);
     const DevState *st = S.st;
     const int slot = ib * BT + tid;
     const double xi = XS[slot], yi = YS[slot], zi = ZS[slot];
+    double vxi = 0.0, vyi = 0.0, vzi = 0.0;
+    if constexpr (LAW != 0) {
+        vxi = VXS[slot];
+        vyi = VYS[slot];
+        vzi = VZS[slot];
+    }
     const int istar = ib * BT >= S.p1 ? 1 : 0;
     double ax = 0.0, ay = 0.0, az = 0.0;
     const int t0 = (int)(((int64_t)c * S.ntiles) / S.nsplit);
@@ -651,17 +835,28 @@ __device__ void force_unit_f64(const SysDesc &S, int ib, int c, double (*sh)[TJ]
         sh[0][tid] = XS[t * TJ + tid];
         sh[1][tid] = YS[t * TJ + tid];
         sh[2][tid] = ZS[t * TJ + tid];
+        if constexpr (LAW != 0) {
+            sh[3][tid] = VXS[t * TJ + tid];
+            sh[4][tid] = VYS[t * TJ + tid];
+            sh[5][tid] = VZS[t * TJ + tid];
+        }
         __syncthreads();
         const int cls = pair_class(istar, t * TJ >= S.p1 ? 1 : 0);
         const double c1 = st->c1d[cls], c2 = st->c2d[cls];
+        const double D = cls == 0 ? st->D1 : (cls == 2 ? st->D2 : 0.5 * (st->D1 + st->D2));
         for (int jj = 0; jj < TJ; ++jj) {
             const double dx = sh[0][jj] - xi;
             const double dy = sh[1][jj] - yi;
             const double dz = sh[2][jj] - zi;
             const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
             const double w = r2 > 0.0 ? rsqrt_f64(r2) : 0.0;
-            const double w3 = w * w * w;
-            const double s = fmin(w3, c1 - c2 * w);
+            double s;
+            if constexpr (LAW == 0) {
+                s = pair_s64<0>(r2, w, dx, dy, dz, 0.0, 0.0, 0.0, D, c1, c2, st);
+            } else {
+                s = pair_s64<LAW>(r2, w, dx, dy, dz, sh[3][jj] - vxi, sh[4][jj] - vyi,
+                                  sh[5][jj] - vzi, D, c1, c2, st);
+            }
             ax = fma(s, dx, ax);
             ay = fma(s, dy, ay);
             az = fma(s, dz, az);
@@ -686,16 +881,17 @@ __device__ void force_unit_f64(const SysDesc &S, int ib, int c, double (*sh)[TJ]
     }
 }
 
+template <int LAW>
 __global__ __launch_bounds__(BT) void k_force_f64(Launch L)
 {
-    __shared__ double sh[3][TJ];
+    __shared__ double sh[LAW == 0 ? 3 : 6][TJ];
     for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
         const int s = find_sys(L, u, false);
         const SysDesc &S = L.sys[s];
         const int local = u - S.unit_begin;
         const int ib = local / S.nsplit;
         const int c = local - ib * S.nsplit;
-        force_unit_f64(S, ib, c, sh);
+        force_unit_f64<LAW>(S, ib, c, sh);
     }
 }
 
@@ -865,6 +1061,7 @@ __global__ __launch_bounds__(BT) void k_finalize_step(Launch L, int do_growth)
                         st->c1f[k] = (float)st->c1d[k];
                         st->c2f[k] = (float)st->c2d[k];
                         st->far2f[k] = (float)(D * D * (1.0 + (double)FAR_MARGIN));
+                        st->lD_f[k] = (float)D;
                     }
                 } else {
                     st->growth_stopped = 1;
@@ -982,8 +1179,8 @@ __global__ __launch_bounds__(BT) void k_diag_partials(Launch L)
 }
 
 // Potential energy: each i sums U(r_ij) over all j != i; the total is halved at the end.
-// U = -A / r for r >= D and A (11 r^2 - 20 D r + 7 D^2) / (2 D^3) inside, A = G m^2: the
-// primitive of the contact law that is continuous at D.
+// Contact law: U = -A / r for r >= D and A (11 r^2 - 20 D r + 7 D^2) / (2 D^3) inside, A = G m^2,
+// the primitive of the law that is continuous at D.
 template <typename T>
 __global__ __launch_bounds__(BT) void k_pe(Launch L)
 {
@@ -1021,10 +1218,20 @@ __global__ __launch_bounds__(BT) void k_pe(Launch L)
                 const double r = sqrt(dx * dx + dy * dy + dz * dz);
                 const double D = Ds[jg >= n1 ? 1 : 0];
                 double U;
-                if (r >= D) {
-                    U = -A / r;
+                if (L.law == 0) {
+                    if (r >= D) {
+                        U = -A / r;
+                    } else {
+                        U = A * (11.0 * r * r - 20.0 * D * r + 7.0 * D * D) / (2.0 * D * D * D);
+                    }
                 } else {
-                    U = A * (11.0 * r * r - 20.0 * D * r + 7.0 * D * D) / (2.0 * D * D * D);
+                    // eqs. (4)-(6), converging branch: -A / (r + eps) plus the overlap energy
+                    // gamma pi (D - r)^3 (r + 3D) / 48 inside D
+                    U = -A / (r + st->leps_d);
+                    if (r < D) {
+                        const double u = D - r;
+                        U += st->gamma * PI_D / 48.0 * u * u * u * (r + 3.0 * D);
+                    }
                 }
                 if (jg != ic && r > 0.0) acc += U;
             }
@@ -1058,6 +1265,107 @@ __global__ __launch_bounds__(BT) void k_finalize_diag(Launch L, int with_pe)
     }
 }
 
+// ------------------------------------------------------------------ accretor-side retention
+
+// Pass 1: per-unit sums of star 1's velocities.
+template <typename T>
+__global__ __launch_bounds__(BT) void k_ret_vsum(Launch L)
+{
+    __shared__ double lds[3][BT / 64];
+    for (int u = blockIdx.x; u < L.total_ounits; u += gridDim.x) {
+        const SysDesc &S = L.sys[find_sys(L, u, true)];
+        const int local = u - S.ounit_begin;
+        const int i = local * BT + threadIdx.x;
+        double v[3] = {0, 0, 0};
+        if (i < S.n1) {
+            v[0] = static_cast<const T *>(S.vx)[i];
+            v[1] = static_cast<const T *>(S.vy)[i];
+            v[2] = static_cast<const T *>(S.vz)[i];
+        }
+        block_sum<3>(v, lds);
+        if (threadIdx.x == 0) {
+            double *r = S.red + (size_t)local * RED_STRIDE + RED_RET;
+            for (int k = 0; k < 3; ++k) r[k] = v[k];
+        }
+    }
+}
+
+// One block per system: star 1's mean velocity.
+__global__ __launch_bounds__(BT) void k_ret_mean(Launch L)
+{
+    __shared__ double lds[3][BT / 64];
+    for (int s = blockIdx.x; s < L.n_sys; s += gridDim.x) {
+        const SysDesc &S = L.sys[s];
+        double v[3] = {0, 0, 0};
+        for (int u = threadIdx.x; u < S.n_ounits; u += BT) {
+            const double *r = S.red + (size_t)u * RED_STRIDE + RED_RET;
+            for (int k = 0; k < 3; ++k) v[k] += r[k];
+        }
+        block_sum<3>(v, lds);
+        if (threadIdx.x == 0) {
+            for (int k = 0; k < 3; ++k) S.st->v1[k] = S.n1 > 0 ? v[k] / (double)S.n1 : 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+// Pass 2: donor elements past the L1 plane of the last step, and those of them bound to the
+// accretor as a point mass n1 m at its centre, moving with its mean velocity:
+// |v - V1|^2 / 2 - G n1 m / |r - C1| < 0, in FP64.
+template <typename T>
+__global__ __launch_bounds__(BT) void k_ret_count(Launch L)
+{
+    __shared__ double lds[2][BT / 64];
+    for (int u = blockIdx.x; u < L.total_ounits; u += gridDim.x) {
+        const SysDesc &S = L.sys[find_sys(L, u, true)];
+        const int local = u - S.ounit_begin;
+        const int i = local * BT + threadIdx.x;
+        const DevState *st = S.st;
+        double v[2] = {0, 0};
+        if (i < S.n && i >= S.n1 && S.n1 > 0 && st->plane_ok) {
+            const double rx = (double)static_cast<const T *>(S.x)[i] - st->com1[0];
+            const double ry = (double)static_cast<const T *>(S.y)[i] - st->com1[1];
+            const double rz = (double)static_cast<const T *>(S.z)[i] - st->com1[2];
+            if (rx * st->e[0] + ry * st->e[1] + rz * st->e[2] < st->xi_cut) {
+                v[0] = 1.0;
+                const double ux = (double)static_cast<const T *>(S.vx)[i] - st->v1[0];
+                const double uy = (double)static_cast<const T *>(S.vy)[i] - st->v1[1];
+                const double uz = (double)static_cast<const T *>(S.vz)[i] - st->v1[2];
+                const double r = sqrt(rx * rx + ry * ry + rz * rz);
+                const double gm1 = st->G * st->m * (double)S.n1;
+                const double energy = 0.5 * (ux * ux + uy * uy + uz * uz) - gm1 / r;
+                v[1] = energy < 0.0 ? 1.0 : 0.0;
+            }
+        }
+        block_sum<2>(v, lds);
+        if (threadIdx.x == 0) {
+            double *r = S.red + (size_t)local * RED_STRIDE + RED_RET + 3;
+            r[0] = v[0];
+            r[1] = v[1];
+        }
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_ret_total(Launch L)
+{
+    __shared__ double lds[2][BT / 64];
+    for (int s = blockIdx.x; s < L.n_sys; s += gridDim.x) {
+        const SysDesc &S = L.sys[s];
+        double v[2] = {0, 0};
+        for (int u = threadIdx.x; u < S.n_ounits; u += BT) {
+            const double *r = S.red + (size_t)u * RED_STRIDE + RED_RET + 3;
+            v[0] += r[0];
+            v[1] += r[1];
+        }
+        block_sum<2>(v, lds);
+        if (threadIdx.x == 0) {
+            S.st->ret_past = (int32_t)v[0];
+            S.st->ret_bound = (int32_t)v[1];
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
 static inline int grid_for(int units)
@@ -1071,18 +1379,20 @@ hipError_t launch_init_state(DevState *st, const DevState &init, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_fill_sorted(void *xs, void *ys, void *zs, int nalloc, int mode, hipStream_t s)
+// sentinel: fill with the padding position; otherwise with zeros (sorted velocities)
+hipError_t launch_fill_sorted(void *xs, void *ys, void *zs, int nalloc, int mode, bool sentinel,
+                              hipStream_t s)
 {
     if (nalloc <= 0) return hipSuccess;
     const dim3 g((nalloc + BT - 1) / BT), b(BT);
     if (mode == 2) {
         hipLaunchKernelGGL(k_fill_sorted<double>, g, b, 0, s, static_cast<double *>(xs),
                            static_cast<double *>(ys), static_cast<double *>(zs), nalloc,
-                           SENTINEL_F64);
+                           sentinel ? SENTINEL_F64 : 0.0);
     } else {
         hipLaunchKernelGGL(k_fill_sorted<float>, g, b, 0, s, static_cast<float *>(xs),
                            static_cast<float *>(ys), static_cast<float *>(zs), nalloc,
-                           SENTINEL_F32);
+                           sentinel ? SENTINEL_F32 : 0.0f);
     }
     return hipGetLastError();
 }
@@ -1105,12 +1415,22 @@ hipError_t launch_forces(const Launch &L, int mode, int max_blocks, hipStream_t 
     // max_blocks > 0: persistent launch, each block loops over units u, u + grid, ...
     const int blocks = max_blocks > 0 ? std::min(L.total_units, max_blocks) : L.total_units;
     const dim3 g(grid_for(blocks)), b(BT);
+    if (L.law != 0 && L.law != 1) return hipErrorInvalidValue;
     if (mode == 0) {
+        if (L.law != 0) return hipErrorInvalidValue;  // eqs. (4)-(6) have no plain FP32 kernel
         hipLaunchKernelGGL((k_force_f32<KI32, false>), g, b, 0, s, L);
     } else if (mode == 1) {
-        hipLaunchKernelGGL(k_force_sym, g, b, 0, s, L);
+        if (L.law == 0) {
+            hipLaunchKernelGGL(k_force_sym, g, b, 0, s, L);
+        } else {
+            hipLaunchKernelGGL(k_force_sym_paper, g, b, 0, s, L);
+        }
     } else {
-        hipLaunchKernelGGL(k_force_f64, g, b, 0, s, L);
+        if (L.law == 0) {
+            hipLaunchKernelGGL(k_force_f64<0>, g, b, 0, s, L);
+        } else {
+            hipLaunchKernelGGL(k_force_f64<1>, g, b, 0, s, L);
+        }
     }
     return hipGetLastError();
 }
@@ -1122,7 +1442,7 @@ hipError_t launch_combine(const Launch &L, int mode, hipStream_t s)
     if (mode == 0) {
         hipLaunchKernelGGL((k_combine<float, false>), g, b, 0, s, L);
     } else if (mode == 1) {
-        hipLaunchKernelGGL(k_combine_sym, g, b, 0, s, L);
+        hipLaunchKernelGGL(k_combine_sym<NB_COMBINE_SEGS>, g, dim3(BT * NB_COMBINE_SEGS), 0, s, L);
     } else {
         hipLaunchKernelGGL((k_combine<double, false>), g, b, 0, s, L);
     }
@@ -1192,6 +1512,29 @@ hipError_t launch_diag(const Launch &L, int mode, int with_pe, hipStream_t s)
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_finalize_diag, dim3(grid_for(L.n_sys)), dim3(BT), 0, s, L, with_pe);
+    return hipGetLastError();
+}
+
+hipError_t launch_retention(const Launch &L, int mode, hipStream_t s)
+{
+    if (L.total_ounits > 0) {
+        const dim3 g(grid_for(L.total_ounits)), b(BT);
+        if (mode == 2) {
+            hipLaunchKernelGGL(k_ret_vsum<double>, g, b, 0, s, L);
+        } else {
+            hipLaunchKernelGGL(k_ret_vsum<float>, g, b, 0, s, L);
+        }
+    }
+    hipLaunchKernelGGL(k_ret_mean, dim3(grid_for(L.n_sys)), dim3(BT), 0, s, L);
+    if (L.total_ounits > 0) {
+        const dim3 g(grid_for(L.total_ounits)), b(BT);
+        if (mode == 2) {
+            hipLaunchKernelGGL(k_ret_count<double>, g, b, 0, s, L);
+        } else {
+            hipLaunchKernelGGL(k_ret_count<float>, g, b, 0, s, L);
+        }
+    }
+    hipLaunchKernelGGL(k_ret_total, dim3(grid_for(L.n_sys)), dim3(BT), 0, s, L);
     return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@ using namespace nbk;
 namespace {
 
 constexpr size_t ALIGN = 256;
+constexpr double PI = 3.14159265358979323846;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -104,10 +105,11 @@ TileCfg tile_config(int64_t n, int64_t n1, int mode)
 }
 
 struct Layout {
-    size_t state, desc, diag, red, pe, log, xs, ys, zs, perm, tbox, units, react, part, total;
+    size_t state, desc, diag, red, pe, log, xs, ys, zs, vxs, vys, vzs, perm, tbox, units, react,
+        part, total;
 };
 
-Layout layout_for(int mode, const TileCfg &c)
+Layout layout_for(int mode, int law, const TileCfg &c)
 {
     Layout L{};
     const size_t elem = mode == NB_FP64 ? sizeof(double) : sizeof(float);
@@ -126,6 +128,10 @@ Layout layout_for(int mode, const TileCfg &c)
     L.xs = take((size_t)c.nalloc * elem);
     L.ys = take((size_t)c.nalloc * elem);
     L.zs = take((size_t)c.nalloc * elem);
+    // sorted velocities: only eqs. (4)-(6) read them
+    L.vxs = take(law == NB_LAW_PAPER ? (size_t)c.nalloc * elem : 0);
+    L.vys = take(law == NB_LAW_PAPER ? (size_t)c.nalloc * elem : 0);
+    L.vzs = take(law == NB_LAW_PAPER ? (size_t)c.nalloc * elem : 0);
     L.perm = take((size_t)c.nalloc * sizeof(int32_t));
     L.tbox = take((size_t)std::max(c.ntiles, 1) * 8 * sizeof(float));
     L.units = take(c.sym ? (size_t)c.n_units * 2 * sizeof(int32_t) : 0);
@@ -193,6 +199,17 @@ bool params_ok(const nb_params *p)
     if (!pos(p->m) || !std::isfinite(p->dt)) return false;
     if (!pos(p->D1) || !pos(p->D2) || !pos(p->q) || !pos(p->a) || !pos(p->R2_0)) return false;
     if (!std::isfinite(p->growth_rate) || p->growth_rate < 0.0) return false;
+    if (p->law != NB_LAW_CONTACT && p->law != NB_LAW_PAPER) return false;
+    if (p->law == NB_LAW_PAPER) {
+        // the pair sums are kept per unit of G m, so the law needs G > 0; the symmetric FP32
+        // kernel and the FP64 kernel implement it, the plain FP32 kernel does not
+        if (p->mode == NB_FP32_PLAIN || !(p->G > 0.0)) return false;
+        if (!std::isfinite(p->eps) || p->eps < 0.0) return false;
+        if (!std::isfinite(p->gamma) || p->gamma < 0.0) return false;
+        if (!std::isfinite(p->beta) || p->beta < 0.0 || p->beta > 1.0) return false;
+        const double gc = p->gamma * PI / (12.0 * p->G * p->m * p->m);
+        if (!std::isfinite(gc) || (p->mode != NB_FP64 && gc > 3.0e38)) return false;
+    }
     return true;
 }
 
@@ -295,6 +312,7 @@ Launch single_launch(const nb_system *s)
     Launch L{};
     L.sys = s->d_desc;
     L.n_sys = 1;
+    L.law = s->p.law;
     L.total_units = s->cfg.n_units;
     L.total_ounits = s->cfg.n_ounits;
     L.total_tunits = s->cfg.ntiles;
@@ -309,6 +327,7 @@ int check_system_list(nb_system *const *sys, int32_t n_sys)
     for (int k = 0; k < n_sys; ++k) {
         if (!sys[k]) return NB_E_INVAL;
         if (sys[k]->p.mode != sys[0]->p.mode) return NB_E_MISMATCH;
+        if (sys[k]->p.law != sys[0]->p.law) return NB_E_MISMATCH;
         for (int j = 0; j < k; ++j) {
             if (sys[j] == sys[k]) return NB_E_INVAL;
         }
@@ -334,6 +353,7 @@ Launch build_table(nb_system *const *sys, int32_t n_sys, std::vector<SysDesc> &t
         combine = combine || sys[k]->cfg.nsplit > 1 || sys[k]->cfg.sym;
     }
     L.n_sys = n_sys;
+    L.law = sys[0]->p.law;
     return L;
 }
 
@@ -391,7 +411,7 @@ int nb_scratch_bytes(const nb_params *p, size_t *out)
 {
     if (!params_ok(p) || !out) return NB_E_INVAL;
     TileCfg c = tile_config(p->n, p->n1, p->mode);
-    *out = layout_for(p->mode, c).total;
+    *out = layout_for(p->mode, p->law, c).total;
     return NB_OK;
 }
 
@@ -410,7 +430,7 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
     }
     if (!b->scratch || !aligned(b->scratch, ALIGN)) return NB_E_INVAL;
     TileCfg cfg = tile_config(p->n, p->n1, p->mode);
-    Layout lay = layout_for(p->mode, cfg);
+    Layout lay = layout_for(p->mode, p->law, cfg);
     if (b->scratch_bytes < lay.total) return NB_E_NOMEM;
 
     nb_system *s = new (std::nothrow) nb_system();
@@ -449,6 +469,11 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
     d.xs = base + lay.xs;
     d.ys = base + lay.ys;
     d.zs = base + lay.zs;
+    const bool paper = p->law == NB_LAW_PAPER;
+    d.vxs = paper ? base + lay.vxs : nullptr;
+    d.vys = paper ? base + lay.vys : nullptr;
+    d.vzs = paper ? base + lay.vzs : nullptr;
+    d.law = p->law;
     d.perm = reinterpret_cast<int32_t *>(base + lay.perm);
     d.tbox = reinterpret_cast<float *>(base + lay.tbox);
     d.npad = cfg.npad;
@@ -498,6 +523,18 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
     init.h_f = (float)init.h_d;
     init.dt_f = (float)p->dt;
     init.growth_on = p->growth_on ? 1 : 0;
+    init.law = p->law;
+    init.gamma = p->gamma;
+    init.beta = p->beta;
+    init.leps_d = p->eps;
+    if (p->law == NB_LAW_PAPER) {
+        init.lgc_d = p->gamma * PI / (12.0 * p->G * p->m * p->m);
+        init.lgcb_d = p->beta * init.lgc_d;
+    }
+    for (int k = 0; k < 3; ++k) init.lD_f[k] = (float)Ds[k];
+    init.leps_f = (float)p->eps;
+    init.lgc_f = (float)init.lgc_d;
+    init.lgcb_f = (float)init.lgcb_d;
 
     hipStream_t st = static_cast<hipStream_t>(stream);
     int rc = NB_OK;
@@ -550,7 +587,12 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
             if (hipMemcpyAsync(d.units, units.data(), units.size() * sizeof(int32_t),
                                hipMemcpyHostToDevice, st) != hipSuccess) { rc = NB_E_HIP; break; }
         }
-        if (launch_fill_sorted(d.xs, d.ys, d.zs, cfg.nalloc, p->mode, st) != hipSuccess) {
+        if (launch_fill_sorted(d.xs, d.ys, d.zs, cfg.nalloc, p->mode, true, st) != hipSuccess) {
+            rc = NB_E_HIP;
+            break;
+        }
+        if (paper && launch_fill_sorted(d.vxs, d.vys, d.vzs, cfg.nalloc, p->mode, false, st) !=
+                         hipSuccess) {
             rc = NB_E_HIP;
             break;
         }
@@ -745,6 +787,19 @@ int nb_diagnostics(nb_system *s, int32_t with_pe, nb_diag *out, void *stream)
     out->growth_stopped = ds.growth_stopped;
     out->nonfinite = ds.nonfinite;
     return ds.nonfinite ? NB_E_NONFINITE : NB_OK;
+}
+
+int nb_retention(nb_system *s, int32_t *n_past, int32_t *n_bound, void *stream)
+{
+    if (!s || !n_past || !n_bound) return NB_E_INVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    NB_TRY(launch_retention(single_launch(s), s->p.mode, st));
+    DevState ds;
+    NB_TRY(hipMemcpyAsync(&ds, s->d_state, sizeof ds, hipMemcpyDeviceToHost, st));
+    NB_TRY(hipStreamSynchronize(st));
+    *n_past = ds.ret_past;
+    *n_bound = ds.ret_bound;
+    return NB_OK;
 }
 
 int nb_l1_log(nb_system *s, int32_t *out_host, int32_t max_steps, int32_t *n_out, void *stream)

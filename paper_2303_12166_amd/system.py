@@ -5,6 +5,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import (
+    LAWS,
     MODES,
     NB_FP64,
     NbBuffers,
@@ -14,6 +15,7 @@ from . import (
     nb_diagnostics,
     nb_forces,
     nb_l1_log,
+    nb_retention,
     nb_scratch_bytes,
     nb_step,
 )
@@ -31,7 +33,8 @@ class System:
     """Device-resident system. ``pos``/``vel`` are (n, 3) host arrays; star 1 is rows [0, n1)."""
 
     def __init__(self, pos, vel, n1, *, G, m, dt, D1, D2, q, a=1.0, R2_0=0.2, growth_rate=1e-4,
-                 growth_on=True, mode="kahan", device=None, stream=None):
+                 growth_on=True, mode="kahan", device=None, stream=None, law="contact",
+                 eps=0.0, gamma=0.0, beta=1.0):
         torch = _torch()
         self.mode = MODES[mode] if isinstance(mode, str) else int(mode)
         dtype = torch.float64 if self.mode == NB_FP64 else torch.float32
@@ -40,9 +43,11 @@ class System:
         vel = np.asarray(vel)
         n = int(pos.shape[0])
         self.n, self.n1 = n, int(n1)
+        self.law = LAWS[law] if isinstance(law, str) else int(law)
         self.params = NbParams(n=n, n1=int(n1), G=G, m=m, dt=dt, D1=D1, D2=D2, q=q, a=a,
                                R2_0=R2_0, growth_rate=growth_rate, growth_on=int(bool(growth_on)),
-                               mode=self.mode)
+                               mode=self.mode, law=self.law, pad=0, eps=eps, gamma=gamma,
+                               beta=beta)
         nbytes = nb_scratch_bytes(self.params)
         k = dict(dtype=dtype, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -92,6 +97,10 @@ class System:
 
     def l1_log(self, max_steps: int = 4096) -> np.ndarray:
         return nb_l1_log(self.handle, max_steps, self.stream)
+
+    def retention(self) -> tuple:
+        """(n_past, n_bound) of the current state (see nb_retention)."""
+        return nb_retention(self.handle, self.stream)
 
     def synchronize(self):
         self.stream.synchronize()

@@ -10,5 +10,7 @@ from .binary import (  # noqa: F401
     particle_counts,
     element_diameter,
     orbital_omega,
+    with_velocity_noise,
+    paper_law_params,
 )
 from .trace import Request, make_trace  # noqa: F401

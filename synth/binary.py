@@ -146,3 +146,30 @@ def make_binary(
         pos=pos,
         vel=vel,
     )
+
+
+def with_velocity_noise(ic: BinaryIC, sigma: float, seed: int) -> BinaryIC:
+    """A copy of ``ic`` whose velocities carry extra isotropic Gaussian noise of std ``sigma``.
+
+    Rigid rotation gives every pair exactly zero radial relative velocity, which would leave the
+    converging/separating choice of eqs. (5)-(6) to rounding; the noise gives each pair a definite
+    sign. Drawn from PCG64(seed), independent of the positions' stream.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    vel = ic.vel + sigma * rng.standard_normal(ic.vel.shape)
+    return dataclasses.replace(ic, vel=vel)
+
+
+def paper_law_params(ic: BinaryIC, strength: float = 200.0, beta: float = 0.5,
+                     eps_frac: float = 0.1) -> dict:
+    """Parameters of the eqs. (4)-(6) element law for the system ``ic`` (an input recipe).
+
+    The paper gives no values. gamma = strength G m^2 / (D1^2 pi R^3), R = D1 / 2, and
+    eps = eps_frac D1. With the defaults the net pair force is repulsive from r = 0 up to a single
+    equilibrium near 0.95 D1 (0.93 D1 for separating pairs at beta = 1/2) and attractive beyond,
+    like the contact law's 10 D / 11; a much weaker gamma or smaller eps lets the softened
+    attraction win at small r, so close pairs collapse towards r ~ eps.
+    """
+    R = 0.5 * ic.D1
+    gamma = strength * ic.G * ic.m * ic.m / (ic.D1 ** 2 * math.pi * R ** 3) if ic.n else 0.0
+    return {"law": "paper", "eps": eps_frac * ic.D1, "gamma": gamma, "beta": beta}

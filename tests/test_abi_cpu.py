@@ -46,8 +46,8 @@ def test_binding_covers_every_declared_symbol(nb):
 
 
 def test_abi_struct_sizes_match_header(nb):
-    # nb_params: 2 int64 + 9 double + 2 int32; nb_diag: 14 double + 1 int64 + 6 int32
-    assert ctypes.sizeof(nb.NbParams) == 8 * 11 + 8
+    # nb_params: 2 int64 + 9 double + 4 int32 + 3 double; nb_diag: 14 double + 1 int64 + 6 int32
+    assert ctypes.sizeof(nb.NbParams) == 8 * 11 + 16 + 24
     assert ctypes.sizeof(nb.NbBuffers) == 8 * 12
     assert ctypes.sizeof(nb.NbDiag) == 8 * 14 + 8 + 4 * 6
 
@@ -91,7 +91,10 @@ def test_tile_override(nb):
 
 @pytest.mark.parametrize("bad", [dict(n=-1), dict(n1=3000), dict(mode=7), dict(D1=0.0),
                                  dict(m=float("nan")), dict(q=-0.5), dict(growth_rate=-1.0),
-                                 dict(n=1 << 31, n1=0)])
+                                 dict(n=1 << 31, n1=0), dict(law=5),
+                                 dict(law=1, mode=0), dict(law=1, beta=1.5),
+                                 dict(law=1, gamma=-1.0), dict(law=1, eps=-0.1),
+                                 dict(law=1, G=0.0)])
 def test_invalid_params_rejected(nb, bad):
     with pytest.raises(nb.NbError) as e:
         nb.nb_scratch_bytes(_params(nb, **bad))
@@ -128,3 +131,11 @@ def test_strerror_and_version(nb):
 def test_timing_without_launches(nb):
     nb.nb_timing_reset()
     assert nb.nb_timing_read() == (0.0, 0)
+
+
+def test_retention_rejects_null_arguments(nb):
+    import ctypes as C
+
+    lib = nb.load()
+    v = C.c_int32(0)
+    assert lib.nb_retention(None, C.byref(v), C.byref(v), None) == nb.NB_E_INVAL

@@ -1,0 +1,243 @@
+"""GPU parity of the paper's element law, eqs. (4)-(6), against the FP64 oracle, via the C ABI.
+
+The law's repulsion depends on the sign of the pair's radial relative velocity, so the inputs
+carry seeded velocity noise (synth.with_velocity_noise); with rigid rotation alone every sign would
+be decided by rounding. Where a contact pair's radial velocity is within a relative 1e-4 of zero
+the two precisions may legitimately take different branches, so rows that hold such a pair are
+left out of the element-wise comparison (they are counted; with these inputs there are few or
+none). Bars: per-element error relative to the largest force <= 1e-5 (FP32 Kahan) and 1e-11
+(FP64), as for the contact law.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import force_error, print_case, require_gpu, sample_rows
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"kahan": 1e-5, "fp64": 1e-11}
+
+
+def law_params(ic, strength=200.0, beta=0.5, eps_frac=0.1):
+    return synth.paper_law_params(ic, strength=strength, beta=beta, eps_frac=eps_frac)
+
+
+def noisy(n, q, seed, sigma=0.05):
+    return synth.with_velocity_noise(synth.make_binary(n, q, seed=seed), sigma, seed + 1000)
+
+
+def tie_rows(pos, vel, n1, D1, D2, rows, rel=1e-4):
+    """Rows with a contact pair whose radial relative velocity is within rel of zero."""
+    n = pos.shape[0]
+    star = np.arange(n) >= n1
+    out = []
+    for i in rows:
+        d = pos - pos[i]
+        r = np.sqrt((d * d).sum(axis=1))
+        Dij = np.where(star == star[i], D2 if star[i] else D1, 0.5 * (D1 + D2))
+        c = (r < Dij) & (r > 0)
+        if not c.any():
+            continue
+        dv = vel[c] - vel[i]
+        dot = (dv * d[c]).sum(axis=1)
+        scale = np.linalg.norm(dv, axis=1) * r[c]
+        if (np.abs(dot) <= rel * scale).any():
+            out.append(i)
+    return np.array(out, dtype=np.int64)
+
+
+def _inputs(ic, mode):
+    if mode == "fp64":
+        return ic.f32_as_f64()
+    p, v = ic.f32()
+    return p.astype(np.float64), v.astype(np.float64)
+
+
+def _compare(a, ref, rows, ties, tol):
+    keep = ~np.isin(rows, ties)
+    assert keep.sum() >= 0.95 * len(rows), f"{(~keep).sum()} of {len(rows)} rows hold a tie"
+    err = force_error(a[keep], ref[keep])
+    return err
+
+
+@pytest.mark.parametrize("beta,eps_frac", [(0.5, 0.1), (1.0, 0.0), (0.0, 0.01)])
+@pytest.mark.parametrize("mode", ["kahan", "fp64"])
+def test_every_row_n2048(mode, beta, eps_frac):
+    nb = require_gpu()
+    ic = noisy(2048, 0.5, seed=0)
+    kw = law_params(ic, beta=beta, eps_frac=eps_frac)
+    print_case("paper law every row", mode, beta, eps_frac)
+    s = nb.System.from_ic(ic, mode=mode, **kw)
+    a = s.accelerations()
+    s.close()
+    p, v = _inputs(ic, mode)
+    ref = oracle.accel_paper(p, v, ic.n1, ic.G, ic.m, ic.D1, ic.D2, kw["eps"], kw["gamma"],
+                             kw["beta"])
+    rows = np.arange(ic.n)
+    ties = tie_rows(p, v, ic.n1, ic.D1, ic.D2, rows)
+    err = _compare(a, ref, rows, ties, TOL[mode])
+    # the overlap term must matter for this test to mean anything
+    grav = oracle.accel(p, ic.n1, ic.G, ic.m, ic.D1, ic.D2)
+    print("paper", mode, beta, "err", err, "ties", len(ties),
+          "law difference", force_error(grav, ref))
+    assert err <= TOL[mode]
+    assert force_error(grav, ref) > 1e-3
+
+
+@pytest.mark.parametrize("n,q", [(1, 0.5), (2, 1.0), (65, 0.8), (257, 0.4), (513, 0.2),
+                                 (3001, 0.3)])
+@pytest.mark.parametrize("mode", ["kahan", "fp64"])
+def test_ragged_sizes(n, q, mode):
+    nb = require_gpu()
+    ic = noisy(n, q, seed=n)
+    kw = law_params(ic)
+    print_case("paper law ragged", n, q, mode)
+    s = nb.System.from_ic(ic, mode=mode, **kw)
+    a = s.accelerations()
+    s.close()
+    p, v = _inputs(ic, mode)
+    ref = oracle.accel_paper(p, v, ic.n1, ic.G, ic.m, ic.D1, ic.D2, kw["eps"], kw["gamma"],
+                             kw["beta"])
+    rows = np.arange(n)
+    ties = tie_rows(p, v, ic.n1, ic.D1, ic.D2, rows)
+    assert _compare(a, ref, rows, ties, TOL[mode]) <= TOL[mode]
+
+
+def test_full_size_sampled_rows_and_momentum():
+    """N = 262,144 (the headline size), Kahan: sampled rows against the oracle, and the summed
+    force, which the symmetric kernel's exact reactions keep at rounding level."""
+    nb = require_gpu()
+    ic = noisy(262144, 0.3, seed=7)
+    kw = law_params(ic)
+    print_case("paper law N=262144 kahan")
+    s = nb.System.from_ic(ic, mode="kahan", **kw)
+    a = s.accelerations()
+    s.close()
+    p, v = _inputs(ic, "kahan")
+    rows = sample_rows(ic.n, ic.n1, 96, seed=5)
+    ref = oracle.accel_paper(p, v, ic.n1, ic.G, ic.m, ic.D1, ic.D2, kw["eps"], kw["gamma"],
+                             kw["beta"], rows=rows)
+    ties = tie_rows(p, v, ic.n1, ic.D1, ic.D2, rows)
+    err = _compare(a[rows], ref, rows, ties, TOL["kahan"])
+    net = np.abs(a.astype(np.float64).sum(axis=0)).max()
+    scale = np.linalg.norm(a.astype(np.float64), axis=1).max()
+    print("N=262144 paper err", err, "ties", len(ties), "net/(n max|a|)", net / (ic.n * scale))
+    assert err <= TOL["kahan"]
+    assert net <= 1e-6 * ic.n * scale
+
+
+@pytest.mark.parametrize("mode,beta,xtol,vtol", [("fp64", 0.5, 1e-11, 1e-10),
+                                                  ("kahan", 1.0, 1e-5, 1e-4),
+                                                  ("kahan", 0.5, 1e-5, 2e-3)])
+def test_trajectory_50_steps(mode, beta, xtol, vtol):
+    """The force inside a step sees the half-step velocities, on both sides.
+
+    With beta < 1 the force jumps when a contact pair's radial velocity changes sign. FP32 and
+    FP64 may put a near-tie pair on different sides of that jump for a step, and each such step
+    moves the pair's velocities by up to dt (1 - beta) gamma V(0) / m (1.8e-4 of max|v| here).
+    The FP32 bar for that case is therefore looser on velocities (2e-3 of max|v|, room for ~10
+    such pair-steps on one element) while positions keep the 1e-5 bar; with beta = 1 there is no
+    jump and the usual bars apply."""
+    nb = require_gpu()
+    ic = noisy(2048, 0.5, seed=3)
+    kw = law_params(ic, beta=beta)
+    print_case("paper law trajectory", mode, beta)
+    s = nb.System.from_ic(ic, mode=mode, **kw)
+    s.step(50)
+    xg, vg = s.positions(), s.velocities()
+    dg = s.diagnostics()
+    s.close()
+    p, v = ic.f32_as_f64()
+    run = oracle.Run(p, v, ic.n1, ic.G, ic.m, 1e-4, ic.D1, ic.D2, ic.q, a=ic.a, R2_0=ic.R2,
+                     law=1, eps=kw["eps"], gamma=kw["gamma"], beta=kw["beta"])
+    run.advance(50)
+    dx = np.abs(xg - run.pos).max()
+    dv = np.abs(vg - run.vel).max() / np.abs(run.vel).max()
+    print("paper trajectory", mode, beta, "max|dx|", dx, "max|dv|/max|v|", dv)
+    assert dx <= xtol * ic.a
+    assert dv <= vtol
+    assert dg["D2"] == run.D2
+
+
+def test_potential_energy_fp64():
+    """Diagnostics PE under eqs. (4)-(6) (the converging-branch potential) against the oracle."""
+    nb = require_gpu()
+    ic = noisy(3000, 0.6, seed=11)
+    kw = law_params(ic, beta=1.0)
+    print_case("paper law PE fp64")
+    s = nb.System.from_ic(ic, mode="fp64", **kw)
+    d = s.diagnostics(with_pe=True)
+    s.close()
+    p, _ = ic.f32_as_f64()
+    pe = oracle.paper_pe(p, ic.n1, ic.G, ic.m, ic.D1, ic.D2, kw["eps"], kw["gamma"])
+    print("PE gpu", d["PE"], "oracle", pe)
+    assert abs(d["PE"] - pe) <= 1e-12 * abs(pe)
+
+
+def test_energy_history_fp64():
+    """Energy (kinetic plus the converging-branch potential) step by step against the oracle's
+    run. With beta < 1 separating pairs repel less than converging ones, so it falls overall."""
+    nb = require_gpu()
+    ic = noisy(2048, 0.5, seed=21, sigma=0.3)
+    kw = law_params(ic, beta=0.2)
+    print_case("paper law energy history fp64")
+    s = nb.System.from_ic(ic, mode="fp64", growth_on=False, **kw)
+    p, v = ic.f32_as_f64()
+    run = oracle.Run(p, v, ic.n1, ic.G, ic.m, 1e-4, ic.D1, ic.D2, ic.q, a=ic.a, R2_0=ic.R2,
+                     growth_on=False, law=1, eps=kw["eps"], gamma=kw["gamma"], beta=kw["beta"])
+
+    def e_oracle():
+        ke = 0.5 * ic.m * (run.vel ** 2).sum()
+        return ke + oracle.paper_pe(run.pos, ic.n1, ic.G, ic.m, ic.D1, ic.D2, kw["eps"],
+                                    kw["gamma"])
+
+    eg, eo = [s.diagnostics(with_pe=True)["E"]], [e_oracle()]
+    for _ in range(20):
+        s.step(1)
+        run.advance(1)
+        eg.append(s.diagnostics(with_pe=True)["E"])
+        eo.append(e_oracle())
+    s.close()
+    eg, eo = np.array(eg), np.array(eo)
+    print("E", eg[0], "->", eg[-1], "max |dE| vs oracle", np.abs(eg - eo).max())
+    assert np.abs(eg - eo).max() <= 1e-10 * abs(eo[0])
+    assert eg[-1] < eg[0]
+
+
+def test_mixed_laws_in_one_batch_are_rejected():
+    nb = require_gpu()
+    ic = noisy(600, 0.5, seed=2)
+    print_case("paper law mixed batch")
+    a = nb.System.from_ic(ic, mode="kahan")
+    b = nb.System.from_ic(ic, mode="kahan", **law_params(ic))
+    with pytest.raises(nb.NbError) as e:
+        nb.nb_step([a.handle, b.handle], 1, a.stream)
+    assert e.value.status == nb.NB_E_MISMATCH
+    # each alone still steps
+    nb.nb_step([a.handle], 1, a.stream)
+    nb.nb_step([b.handle], 1, b.stream)
+    assert a.diagnostics()["step"] == 1 and b.diagnostics()["step"] == 1
+    a.close()
+    b.close()
+
+
+def test_batched_paper_law_matches_alone():
+    """Several law-1 systems stepped in one launch give the same bits as each stepped alone."""
+    nb = require_gpu()
+    ics = [noisy(n, q, seed=n) for n, q in ((700, 0.4), (1500, 0.9), (300, 0.2))]
+    print_case("paper law batch vs alone")
+    alone = []
+    for ic in ics:
+        s = nb.System.from_ic(ic, mode="kahan", **law_params(ic))
+        s.step(5)
+        alone.append((s.positions(), s.velocities()))
+        s.close()
+    sys_ = [nb.System.from_ic(ic, mode="kahan", **law_params(ic)) for ic in ics]
+    nb.nb_step([s.handle for s in sys_], 5, sys_[0].stream)
+    for s, (x, v) in zip(sys_, alone):
+        assert np.array_equal(s.positions(), x)
+        assert np.array_equal(s.velocities(), v)
+        s.close()

@@ -65,3 +65,21 @@ def test_trace_shape():
     assert [t.seed for t in tr] == list(range(256))
     span = tr[-1].t_arrive
     assert 8.0 < span < 18.0  # 255 gaps of mean 1/20 s
+
+
+def test_paper_law_recipe_has_one_equilibrium_inside_contact():
+    """The eqs. (4)-(6) parameter recipe: the oracle's pair force is repulsive from r = 0 up to
+    one equilibrium just inside D and attractive beyond, for converging and separating pairs."""
+    import oracle
+
+    ic = synth.make_binary(2048, 0.5, seed=0)
+    kw = synth.paper_law_params(ic)
+    R = 0.5 * ic.D1
+    xs = np.linspace(1e-4, 2.0, 4001) * ic.D1
+    for vr in (-1.0, 1.0):
+        f = np.array([oracle.paper_force(r, vr, R, ic.G, ic.m, ic.m, kw["eps"], kw["gamma"],
+                                         kw["beta"]) for r in xs])
+        flips = np.flatnonzero(np.diff(np.sign(f)) != 0)
+        assert len(flips) == 1
+        assert 0.9 < xs[flips[0]] / ic.D1 < 0.97
+        assert f[0] < 0 and f[-1] > 0
