@@ -55,8 +55,9 @@ def kernel_source_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def hbm_traffic(workload: str, mode: str):
-    """HBM bytes per force launch from committed rocprofv3 counters, if they match this source."""
+def counter_record(workload: str, mode: str):
+    """The committed rocprofv3 counter record of this workload's force kernel, if it was taken
+    with this kernel source (HBM bytes per launch, VALU instructions per pair)."""
     try:
         with open(COUNTERS_FILE) as f:
             rec = json.load(f)
@@ -65,7 +66,7 @@ def hbm_traffic(workload: str, mode: str):
     entry = rec.get("%s:%s" % (workload, mode))
     if not entry or entry.get("kernel_sha") != kernel_source_sha():
         return None
-    return entry.get("bytes_per_launch")
+    return entry
 
 
 def cpu_model() -> str:
@@ -440,6 +441,7 @@ def main() -> int:
     value = inter * steps / elapsed
     avg_s = force_ms / max(launches, 1) / 1e3
     peak = PEAK_FP64_TFLOPS if mode == "fp64" else PEAK_FP32_TFLOPS
+    counters = counter_record(args.workload + (":paper" if law else ""), mode)
     achieved = FLOPS_PER_INTERACTION * inter / avg_s / 1e12 if avg_s > 0 else 0.0
     roofline = {
         "bound": "alu",
@@ -447,7 +449,7 @@ def main() -> int:
         "peak": peak,
         "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4),
-        "traffic": hbm_traffic(args.workload + (":paper" if law else ""), mode),
+        "traffic": (counters or {}).get("bytes_per_launch"),
         "kernel": (PAPER_KERNEL_NAMES if law else KERNEL_NAMES)[mode],
         "flops_per_interaction": FLOPS_PER_INTERACTION,
         "avg_launch_ms": round(avg_s * 1e3, 4),
@@ -455,6 +457,14 @@ def main() -> int:
         "flops_per_launch": FLOPS_PER_INTERACTION * inter,
         "kernel_interactions_per_s": inter / avg_s if avg_s > 0 else 0.0,
     }
+    if counters:
+        roofline["counters"] = {
+            "source": "profiles/force_counters.json (rocprofv3, same kernel source)",
+            "valu_lane_instructions_per_pair": counters.get("valu_lane_instructions_per_pair"),
+            "trans_lane_instructions_per_pair": counters.get("trans_lane_instructions_per_pair"),
+            "hbm_bytes_per_launch": counters.get("bytes_per_launch"),
+            "algorithmic_bytes_per_launch": counters.get("algorithmic_bytes_per_launch"),
+        }
 
     out = {
         "metric": METRIC,
