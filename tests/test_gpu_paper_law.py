@@ -241,3 +241,26 @@ def test_batched_paper_law_matches_alone():
         assert np.array_equal(s.positions(), x)
         assert np.array_equal(s.velocities(), v)
         s.close()
+
+
+@pytest.mark.parametrize("mode", ["kahan", "fp64"])
+def test_graph_replays_match_nb_step(mode):
+    """A captured graph of law-1 steps, replayed three times with eager work between replays,
+    leaves the same bits as nb_step."""
+    nb = require_gpu()
+    ic = noisy(5000, 0.4, seed=41)
+    kw = law_params(ic)
+    print_case("paper law graph vs step", mode)
+    a = nb.System.from_ic(ic, mode=mode, **kw)
+    b = nb.System.from_ic(ic, mode=mode, **kw)
+    a.step(15)
+    g = nb.nb_graph_create([b.handle], 5, b.stream)
+    for k in range(3):
+        nb.nb_graph_launch(g, b.stream)
+        b.synchronize()
+        assert b.diagnostics()["step"] == 5 * (k + 1)
+    nb.nb_graph_destroy(g)
+    assert np.array_equal(a.positions(), b.positions())
+    assert np.array_equal(a.velocities(), b.velocities())
+    a.close()
+    b.close()
