@@ -26,6 +26,9 @@ namespace nbk {
 #ifndef NB_COMBINE_SEGS
 #define NB_COMBINE_SEGS 1  // threads per element in the symmetric combine (1, 2 or 4)
 #endif
+#ifndef NB_SYM_ROWS
+#define NB_SYM_ROWS 1      // tile rows per block of the symmetric kernel (1 or 2)
+#endif
 #ifndef NB_SYM_WAVES_PER_EU
 #define NB_SYM_WAVES_PER_EU 6
 #endif
@@ -52,6 +55,7 @@ constexpr int BT = 256;          // threads per block, every kernel
 constexpr int TJ = 256;          // j elements staged in LDS per tile (one per thread)
 constexpr int KI32 = NB_KI32;    // i elements per lane, FP32 force kernel
 constexpr int KI64 = 1;          // i elements per lane, FP64 force kernel
+constexpr int SYM_ROWS = NB_SYM_ROWS;  // tile rows per block of the symmetric kernel
 constexpr int RED_STRIDE = 32;   // doubles per O(N)-unit partial record
 constexpr int RED_STEP = 0;      // record slots [0, 16): per-step sums (COMs, flags, L1 counts)
 constexpr int RED_DIAG = 16;     // record slots [16, 32): diagnostics sums
@@ -124,9 +128,10 @@ struct SysDesc {
     int32_t n_peunits, pad;
     int32_t npad, p1, nalloc, ntiles;  // sorted layout (see above)
     int32_t tunit_begin, pad2;         // prefix offset of this system's tiles in the launch
-    // symmetric FP32 kernel (Kahan mode): work units (row I, chunk c) and reaction partials
-    int32_t *units;       // n_units pairs (I, c)
-    float *react;         // 3 * TJ * ntiles (ntiles - 1) / 2 reaction sums
+    // symmetric FP32 kernel (Kahan mode): work units (row group g, chunk c) and reaction
+    // partials, per group g the tiles after its first row: 3 * TJ * sum_g (T - SYM_ROWS g - 1)
+    int32_t *units;       // n_units pairs (g, c)
+    float *react;
     int32_t ch, sym;      // tiles per chunk; 1 when the symmetric kernel is used
     void *vxs, *vys, *vzs;  // sorted velocities (eqs. 4-6 only; null otherwise)
     int32_t law, pad3;

@@ -547,18 +547,27 @@ __device__ __forceinline__ LawF law_f(const DevState *st, int cls)
     return K;
 }
 
-// Reactions of row I are stored row after row: row I covers slots [TJ (I + 1), npad), three
-// components one after the other.
-__device__ __forceinline__ size_t react_row_offset(int I, int npad)
+// Reactions are stored per row group g (tile rows SYM_ROWS g .. SYM_ROWS g + SYM_ROWS - 1) for the
+// tiles t after the group's first row, t = SYM_ROWS g + 1 .. T - 1: three components one after the
+// other, each (T - SYM_ROWS g - 1) TJ floats. Group g starts after
+// sum_{g' < g} 3 TJ (T - SYM_ROWS g' - 1) = 3 TJ (g (T - 1) - SYM_ROWS g (g - 1) / 2) floats.
+__device__ __forceinline__ size_t react_group_offset(int g, int ntiles)
 {
-    return (size_t)3 * ((size_t)I * npad - (size_t)TJ * I * (I + 1) / 2);
+    return (size_t)3 * TJ *
+           ((size_t)g * (ntiles - 1) - (size_t)SYM_ROWS * (size_t)g * (size_t)(g - 1) / 2);
 }
 
+// One work unit of the symmetric kernel: row group g against chunk c of its tiles. The block
+// has SYM_ROWS x 4 waves; waves 4r .. 4r + 3 own the 256 slots of tile row I = SYM_ROWS g + r (one
+// i per lane). Each j tile t of the chunk is staged once in LDS for all rows; row I evaluates
+// t = I one-sided, t > I with reactions, and skips t < I. The reactions of all rows on tile t
+// are added (rows in order, waves in order within a row) and stored once per (group, tile).
 template <int LAW>
-__device__ void force_unit_sym(const SysDesc &S, int I, int c, float4 *sj, float4 *sv,
+__device__ void force_unit_sym(const SysDesc &S, int grp, int c, float4 *sj, float4 *sv,
                                float (*rw)[3][TJ])
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = tid / TJ, lt = tid % TJ;
     const float *__restrict__ XS = static_cast<const float *>(S.xs);
     const float *__restrict__ YS = static_cast<const float *>(S.ys);
     const float *__restrict__ ZS = static_cast<const float *>(S.zs);
@@ -566,7 +575,11 @@ __device__ void force_unit_sym(const SysDesc &S, int I, int c, float4 *sj, float
     const float *__restrict__ VYS = static_cast<const float *>(S.vys);
     const float *__restrict__ VZS = static_cast<const float *>(S.vzs);
     const DevState *st = S.st;
-    const int slot = I * TJ + tid;
+    const int T = S.ntiles;
+    const int g0 = SYM_ROWS * grp;            // first tile row of the group
+    const int I = g0 + r;                     // this wave's tile row
+    const bool row_ok = I < T;                // the last group may be short
+    const int slot = (row_ok ? I : g0) * TJ + lt;
     IState<1> Ist;
     Ist.x[0] = XS[slot];
     Ist.y[0] = YS[slot];
@@ -574,7 +587,7 @@ __device__ void force_unit_sym(const SysDesc &S, int I, int c, float4 *sj, float
     Ist.ax[0] = Ist.ay[0] = Ist.az[0] = 0.0f;
     float4 vi = make_float4(0.f, 0.f, 0.f, 0.f);
     if constexpr (LAW != 0) vi = make_float4(VXS[slot], VYS[slot], VZS[slot], 0.0f);
-    const bool real = S.perm[slot] >= 0;
+    const bool real = row_ok && S.perm[slot] >= 0;
     float lo[3], hi[3];
     lo[0] = wave_min(real ? Ist.x[0] : INFINITY);
     lo[1] = wave_min(real ? Ist.y[0] : INFINITY);
@@ -587,42 +600,51 @@ __device__ void force_unit_sym(const SysDesc &S, int I, int c, float4 *sj, float
     const float far2a = st->far2f[istar], far2b = st->far2f[istar + 1];
 
     float sumx = 0.f, sumy = 0.f, sumz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
-    const int t0 = I + c * S.ch;
-    const int t1 = min(S.ntiles, t0 + S.ch);
-    const int npad = S.npad;
+    const int t0 = g0 + c * S.ch;
+    const int t1 = min(T, t0 + S.ch);
     float *R = S.react;
-    const size_t roff = react_row_offset(I, npad);
-    const size_t rlen = (size_t)npad - (size_t)TJ * (I + 1);
+    const size_t roff = react_group_offset(grp, T);
+    const size_t rlen = (size_t)(T - g0 - 1) * TJ;
+    // tile staging: with one row per block every thread loads its slot's position (and
+    // velocity); with two, the first row's threads load positions and the second's velocities
+    const bool load_pos = SYM_ROWS == 1 || r == 0;
+    const bool load_vel = LAW != 0 && (SYM_ROWS == 1 || r == 1);
     float px = 0.f, py = 0.f, pz = 0.f, qx = 0.f, qy = 0.f, qz = 0.f;
     if (t0 < t1) {
-        px = XS[t0 * TJ + tid];
-        py = YS[t0 * TJ + tid];
-        pz = ZS[t0 * TJ + tid];
-        if constexpr (LAW != 0) {
-            qx = VXS[t0 * TJ + tid];
-            qy = VYS[t0 * TJ + tid];
-            qz = VZS[t0 * TJ + tid];
+        if (load_pos) {
+            px = XS[t0 * TJ + lt];
+            py = YS[t0 * TJ + lt];
+            pz = ZS[t0 * TJ + lt];
+        }
+        if (load_vel) {
+            qx = VXS[t0 * TJ + lt];
+            qy = VYS[t0 * TJ + lt];
+            qz = VZS[t0 * TJ + lt];
         }
     }
     for (int t = t0; t < t1; ++t) {
         {
-            const int at = sym_slot(tid);
-            sj[at] = make_float4(px, py, pz, 0.0f);
-            if constexpr (LAW != 0) sv[at] = make_float4(qx, qy, qz, 0.0f);
-            if constexpr (NB_SYM_DUP != 0) {
-                sj[at + 64] = make_float4(px, py, pz, 0.0f);
-                if constexpr (LAW != 0) sv[at + 64] = make_float4(qx, qy, qz, 0.0f);
+            const int at = sym_slot(lt);
+            if (load_pos) {
+                sj[at] = make_float4(px, py, pz, 0.0f);
+                if constexpr (NB_SYM_DUP != 0) sj[at + 64] = make_float4(px, py, pz, 0.0f);
+            }
+            if (load_vel) {
+                sv[at] = make_float4(qx, qy, qz, 0.0f);
+                if constexpr (NB_SYM_DUP != 0) sv[at + 64] = make_float4(qx, qy, qz, 0.0f);
             }
         }
         __syncthreads();
         if (t + 1 < t1) {
-            px = XS[(t + 1) * TJ + tid];
-            py = YS[(t + 1) * TJ + tid];
-            pz = ZS[(t + 1) * TJ + tid];
-            if constexpr (LAW != 0) {
-                qx = VXS[(t + 1) * TJ + tid];
-                qy = VYS[(t + 1) * TJ + tid];
-                qz = VZS[(t + 1) * TJ + tid];
+            if (load_pos) {
+                px = XS[(t + 1) * TJ + lt];
+                py = YS[(t + 1) * TJ + lt];
+                pz = ZS[(t + 1) * TJ + lt];
+            }
+            if (load_vel) {
+                qx = VXS[(t + 1) * TJ + lt];
+                qy = VYS[(t + 1) * TJ + lt];
+                qz = VZS[(t + 1) * TJ + lt];
             }
         }
         const bool jstar = t * TJ >= S.p1;
@@ -634,9 +656,9 @@ __device__ void force_unit_sym(const SysDesc &S, int I, int c, float4 *sj, float
         K.eps = Ka.eps;
         K.gc = Ka.gc;
         K.gcb = Ka.gcb;
-        if (t == I) {
+        if (row_ok && t == I) {
             diag_tile<LAW>(sj, sv, Ist, vi, K);
-        } else {
+        } else if (row_ok && t > I) {
             const float *bx = S.tbox + (size_t)t * 8;
             const float gx = fmaxf(0.0f, fmaxf(bx[0] - hi[0], lo[0] - bx[4]));
             const float gy = fmaxf(0.0f, fmaxf(bx[1] - hi[1], lo[1] - bx[5]));
@@ -650,11 +672,24 @@ __device__ void force_unit_sym(const SysDesc &S, int I, int c, float4 *sj, float
                 sym_tile<true, LAW>(sj, sv, Ist, vi, K, rw[wave][0], rw[wave][1], rw[wave][2],
                                     lane);
             }
+        }
+        if (t > g0) {
+            // tile t lies after the group's first row, so at least one row left reactions
             __syncthreads();
-            const size_t at = roff + (size_t)t * TJ + tid - (size_t)TJ * (I + 1);
+            if (tid < TJ) {
+                const size_t at = roff + (size_t)(t - g0 - 1) * TJ + lt;
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                R[at + d * rlen] = ((rw[0][d][tid] + rw[1][d][tid]) + rw[2][d][tid]) + rw[3][d][tid];
+                for (int d = 0; d < 3; ++d) {
+                    float v = ((rw[0][d][lt] + rw[1][d][lt]) + rw[2][d][lt]) + rw[3][d][lt];
+#pragma unroll
+                    for (int q = 1; q < SYM_ROWS; ++q) {
+                        if (t > g0 + q && g0 + q < T) {
+                            v = (((v + rw[4 * q][d][lt]) + rw[4 * q + 1][d][lt]) +
+                                 rw[4 * q + 2][d][lt]) + rw[4 * q + 3][d][lt];
+                        }
+                    }
+                    R[at + d * rlen] = v;
+                }
             }
         }
         kahan_add(sumx, cx, Ist.ax[0]);
@@ -673,10 +708,10 @@ __device__ void force_unit_sym(const SysDesc &S, int I, int c, float4 *sj, float
     }
 }
 
-__global__ __launch_bounds__(BT) NB_SYM_ATTR void k_force_sym(Launch L)
+__global__ __launch_bounds__(BT * SYM_ROWS) NB_SYM_ATTR void k_force_sym(Launch L)
 {
     __shared__ float4 sj[SYM_TILE];
-    __shared__ __attribute__((aligned(16))) float rw[BT / 64][3][TJ];
+    __shared__ __attribute__((aligned(16))) float rw[4 * SYM_ROWS][3][TJ];
     for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
         const SysDesc &S = L.sys[find_sys(L, u, false)];
         const int2 ic = reinterpret_cast<const int2 *>(S.units)[u - S.unit_begin];
@@ -685,11 +720,11 @@ __global__ __launch_bounds__(BT) NB_SYM_ATTR void k_force_sym(Launch L)
 }
 
 // The same under eqs. (4)-(6): each tile also stages the sorted half-step velocities.
-__global__ __launch_bounds__(BT) NB_SYM_PAPER_ATTR void k_force_sym_paper(Launch L)
+__global__ __launch_bounds__(BT * SYM_ROWS) NB_SYM_PAPER_ATTR void k_force_sym_paper(Launch L)
 {
     __shared__ float4 sj[SYM_TILE];
     __shared__ float4 sv[SYM_TILE];
-    __shared__ __attribute__((aligned(16))) float rw[BT / 64][3][TJ];
+    __shared__ __attribute__((aligned(16))) float rw[4 * SYM_ROWS][3][TJ];
     for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
         const SysDesc &S = L.sys[find_sys(L, u, false)];
         const int2 ic = reinterpret_cast<const int2 *>(S.units)[u - S.unit_begin];
@@ -697,11 +732,12 @@ __global__ __launch_bounds__(BT) NB_SYM_PAPER_ATTR void k_force_sym_paper(Launch
     }
 }
 
-// a = G m (sum of the row's chunk partials, then the reactions of rows 0 .. J-1), scattered to
-// the element's own index. Each element's rows are cut into SEGS contiguous runs, summed by SEGS
-// threads at once (more loads in flight for the long rows of the last tiles); each run is a
-// Kahan sum in row order (the first run starts with the chunk partials), and the run results are
-// added in run order with Kahan compensation. The order is fixed, so the result is too.
+// a = G m (sum of the element's own chunk partials, then the reactions of every row group with a
+// row before the element's tile, in group order), scattered to the element's own index. Each
+// element's groups are cut into SEGS contiguous runs, summed by SEGS threads at once; each run is
+// a Kahan sum in group order (the first run starts with the chunk partials), and the run
+// results are added in run order with Kahan compensation. The order is fixed, so the result is
+// too.
 template <int SEGS>
 __global__ __launch_bounds__(BT * SEGS) void k_combine_sym(Launch L)
 {
@@ -710,14 +746,16 @@ __global__ __launch_bounds__(BT * SEGS) void k_combine_sym(Launch L)
     for (int u = blockIdx.x; u < L.total_tunits; u += gridDim.x) {
         const SysDesc &S = L.sys[find_tile_sys(L, u)];
         const int J = u - S.tunit_begin;
+        const int T = S.ntiles;
         const int slot = J * TJ + e;
         const int idx = S.perm[slot];
         const float *P = static_cast<const float *>(S.part);
         const float *R = S.react;
         const size_t na = S.nalloc;
-        const int npad = S.npad;
-        const int cj = (S.ntiles - J + S.ch - 1) / S.ch;
-        const int r0 = (int)(((int64_t)J * k) / SEGS), r1 = (int)(((int64_t)J * (k + 1)) / SEGS);
+        const int own = J / SYM_ROWS;                        // the element's own group
+        const int cj = (T - SYM_ROWS * own + S.ch - 1) / S.ch;  // its chunk count
+        const int ng = (J + SYM_ROWS - 1) / SYM_ROWS;          // groups with a row before J
+        const int r0 = (int)(((int64_t)ng * k) / SEGS), r1 = (int)(((int64_t)ng * (k + 1)) / SEGS);
         float out[3] = {0.f, 0.f, 0.f};
         if (idx >= 0) {
             for (int d = 0; d < 3; ++d) {
@@ -726,26 +764,26 @@ __global__ __launch_bounds__(BT * SEGS) void k_combine_sym(Launch L)
                     for (int c = 0; c < cj; ++c)
                         kahan_add(sum, comp, P[(size_t)c * 3 * na + d * na + slot]);
                 }
-                // rows are read eight at a time (independent loads in flight), then added in
-                // row order; the arithmetic is the same as one row at a time
-                size_t off = react_row_offset(r0, npad);
-                size_t len = (size_t)npad - (size_t)TJ * (r0 + 1);
-                int I = r0;
-                for (; I + 8 <= r1; I += 8) {
+                // groups are read eight at a time (independent loads in flight), then added in
+                // group order; the arithmetic is the same as one group at a time
+                size_t off = react_group_offset(r0, T);
+                size_t len = (size_t)(T - SYM_ROWS * r0 - 1) * TJ;
+                int g = r0;
+                for (; g + 8 <= r1; g += 8) {
                     float v[8];
 #pragma unroll
                     for (int q = 0; q < 8; ++q) {
-                        v[q] = R[off + d * len + slot - (size_t)TJ * (I + q + 1)];
+                        v[q] = R[off + d * len + slot - (size_t)TJ * (SYM_ROWS * (g + q) + 1)];
                         off += 3 * len;
-                        len -= TJ;
+                        len -= (size_t)SYM_ROWS * TJ;
                     }
 #pragma unroll
                     for (int q = 0; q < 8; ++q) kahan_add(sum, comp, v[q]);
                 }
-                for (; I < r1; ++I) {
-                    kahan_add(sum, comp, R[off + d * len + slot - (size_t)TJ * (I + 1)]);
+                for (; g < r1; ++g) {
+                    kahan_add(sum, comp, R[off + d * len + slot - (size_t)TJ * (SYM_ROWS * g + 1)]);
                     off += 3 * len;
-                    len -= TJ;
+                    len -= (size_t)SYM_ROWS * TJ;
                 }
                 out[d] = sum - comp;
             }
@@ -1421,9 +1459,9 @@ hipError_t launch_forces(const Launch &L, int mode, int max_blocks, hipStream_t 
         hipLaunchKernelGGL((k_force_f32<KI32, false>), g, b, 0, s, L);
     } else if (mode == 1) {
         if (L.law == 0) {
-            hipLaunchKernelGGL(k_force_sym, g, b, 0, s, L);
+            hipLaunchKernelGGL(k_force_sym, g, dim3(BT * SYM_ROWS), 0, s, L);
         } else {
-            hipLaunchKernelGGL(k_force_sym_paper, g, b, 0, s, L);
+            hipLaunchKernelGGL(k_force_sym_paper, g, dim3(BT * SYM_ROWS), 0, s, L);
         }
     } else {
         if (L.law == 0) {

@@ -85,16 +85,21 @@ TileCfg tile_config(int64_t n, int64_t n1, int mode)
         }
     }
     if (mode == NB_FP32_KAHAN && c.ntiles > 0) {
-        // symmetric kernel: row I covers tiles I .. T-1 in chunks of ch tiles; nsplit is the
-        // chunk count of the longest row
+        // symmetric kernel: group g holds tile rows SYM_ROWS g .. SYM_ROWS g + SYM_ROWS - 1 and
+        // covers tiles SYM_ROWS g .. T-1 in chunks of ch tiles; its reactions are stored for the
+        // tiles after its first row. nsplit is the chunk count of the longest group.
         c.sym = 1;
         c.ch = std::max(1, (c.ntiles + std::max(ns, 1) - 1) / std::max(ns, 1));
         c.nsplit = (c.ntiles + c.ch - 1) / c.ch;
         c.jchunk = c.ch * TJ;
-        int64_t units = 0;
-        for (int k = 1; k <= c.ntiles; ++k) units += (k + c.ch - 1) / c.ch;
+        int64_t units = 0, react_tiles = 0;
+        for (int g = 0; g * SYM_ROWS < c.ntiles; ++g) {
+            const int span = c.ntiles - g * SYM_ROWS;
+            units += (span + c.ch - 1) / c.ch;
+            react_tiles += span - 1;
+        }
         c.n_units = (int)units;
-        c.react_floats = (size_t)3 * TJ * (size_t)c.ntiles * (size_t)(c.ntiles - 1) / 2;
+        c.react_floats = (size_t)3 * TJ * (size_t)react_tiles;
         return c;
     }
     // chunk c covers tiles [c ntiles / nsplit, (c + 1) ntiles / nsplit)
@@ -567,13 +572,15 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
                            hipMemcpyHostToDevice, st) != hipSuccess) { rc = NB_E_HIP; break; }
         std::vector<int32_t> units;
         if (cfg.sym) {
-            // (row, chunk) pairs, full-length chunks first (each row's last chunk may be short)
+            // (row group, chunk) pairs, full-length chunks first (each group's last chunk may be
+            // short)
             std::vector<std::pair<int, std::pair<int, int>>> order;
-            for (int I = 0; I < cfg.ntiles; ++I) {
-                const int rows = (cfg.ntiles - I + cfg.ch - 1) / cfg.ch;
-                for (int c = 0; c < rows; ++c) {
-                    const int len = std::min(cfg.ch, cfg.ntiles - I - c * cfg.ch);
-                    order.push_back({-len, {I, c}});
+            for (int g = 0; g * SYM_ROWS < cfg.ntiles; ++g) {
+                const int span = cfg.ntiles - g * SYM_ROWS;
+                const int chunks = (span + cfg.ch - 1) / cfg.ch;
+                for (int c = 0; c < chunks; ++c) {
+                    const int len = std::min(cfg.ch, span - c * cfg.ch);
+                    order.push_back({-len, {g, c}});
                 }
             }
             std::stable_sort(order.begin(), order.end(),
