@@ -1,0 +1,80 @@
+"""Edge cases of the GPU path: an empty system alone and inside a batch, the largest size tried
+(N = 1,048,576, about 26 GB of reaction buffer in Kahan mode) against the oracle on sampled
+rows, and a system whose stars are both a single element."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import force_error, print_case, require_gpu, sample_rows
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("mode", ["plain", "kahan", "fp64"])
+def test_empty_system(mode):
+    nb = require_gpu()
+    print_case("empty system", mode)
+    z = np.zeros((0, 3))
+    s = nb.System(z, z, 0, G=1.0, m=1e-3, dt=1e-4, D1=0.01, D2=0.01, q=0.5, mode=mode)
+    s.forces()
+    s.step(3)
+    d = s.diagnostics(with_pe=True)
+    assert d["step"] == 3 and d["nonfinite"] == 0 and d["n_past_L1"] == 0
+    assert d["KE"] == 0.0 and d["PE"] == 0.0
+    assert s.retention() == (0, 0)
+    assert s.positions().shape == (0, 3)
+    s.close()
+
+
+@pytest.mark.parametrize("mode", ["kahan", "fp64"])
+def test_empty_system_inside_a_batch(mode):
+    nb = require_gpu()
+    print_case("empty system in batch", mode)
+    ic = synth.make_binary(3000, 0.5, seed=8)
+    z = np.zeros((0, 3))
+
+    def empty():
+        return nb.System(z, z, 0, G=1.0, m=1e-3, dt=1e-4, D1=0.01, D2=0.01, q=0.5, mode=mode)
+
+    alone = nb.System.from_ic(ic, mode=mode)
+    alone.step(6)
+    e1, full, e2 = empty(), nb.System.from_ic(ic, mode=mode), empty()
+    nb.step_many([e1, full, e2], 6)
+    assert np.array_equal(alone.positions(), full.positions())
+    assert np.array_equal(alone.velocities(), full.velocities())
+    assert e1.diagnostics()["step"] == 6 and e2.diagnostics()["step"] == 6
+    for s in (alone, e1, full, e2):
+        s.close()
+
+
+@pytest.mark.parametrize("mode", ["kahan", "fp64"])
+def test_one_element_per_star(mode):
+    nb = require_gpu()
+    print_case("one element per star", mode)
+    pos = np.array([[-0.3, 0.0, 0.0], [0.7, 0.0, 0.0]])
+    vel = np.array([[0.0, -0.5, 0.0], [0.0, 1.0, 0.0]])
+    s = nb.System(pos, vel, 1, G=1.0, m=0.5, dt=1e-4, D1=0.05, D2=0.04, q=0.5, mode=mode)
+    a = s.accelerations()
+    s.close()
+    ref = oracle.accel(pos, 1, 1.0, 0.5, 0.05, 0.04)
+    assert force_error(a, ref) <= (1e-6 if mode == "kahan" else 1e-14)
+    # Newton: equal and opposite
+    assert np.allclose(a[0], -a[1], rtol=1e-6, atol=0)
+
+
+def test_largest_size_sampled_rows_kahan():
+    nb = require_gpu()
+    n, q = 1048576, 0.5
+    ic = synth.make_binary(n, q, seed=0)
+    print_case("largest size", n, q)
+    s = nb.System.from_ic(ic, mode="kahan")
+    a = s.accelerations()
+    s.close()
+    rows = sample_rows(n, ic.n1, 64, seed=3)
+    p, _ = ic.f32_as_f64()
+    ref = oracle.accel(p, ic.n1, ic.G, ic.m, ic.D1, ic.D2, rows=rows)
+    err = force_error(a[rows], ref)
+    print("N=1048576 kahan max rel err", err)
+    assert err <= 1e-5
