@@ -134,7 +134,10 @@ int nb_forces(nb_system *s, void *stream);
  * stops growth for good) and the L1 count. n_sys = 1 is the plain path. With n_sys > 1 all
  * systems advance together: each kernel of a step is one launch over all systems' work (a
  * segment table), and each system's results are bitwise the same as when it runs alone. The
- * systems must share one mode and must be distinct. Asynchronous on `stream`. */
+ * systems must be distinct (NB_E_INVAL) and share one mode and one element law (NB_E_MISMATCH).
+ * The library keeps the segment table of the last multi-system call per device and stream;
+ * calls on one stream are ordered, calls on different streams do not share a table.
+ * Asynchronous on `stream`. */
 int nb_step(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *stream);
 
 /* Captures n_steps steps of the listed systems (exactly the work nb_step would queue for them)

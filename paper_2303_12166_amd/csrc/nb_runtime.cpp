@@ -228,8 +228,11 @@ struct Timing {
 } g_timing;
 
 // Library-owned segment table for multi-system steps, one per device.
+// Segment table of the last multi-system nb_step, one per (device, stream): work queued on one
+// stream never reads a table that a call on another stream rewrites.
 struct BatchTable {
     int device = -1;
+    hipStream_t stream = nullptr;
     SysDesc *d = nullptr;
     SysDesc *h = nullptr;  // pinned staging
     int cap = 0;
@@ -650,12 +653,13 @@ int nb_step(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *stream)
     std::lock_guard<std::mutex> g(g_batch_mu);
     BatchTable *bt = nullptr;
     for (BatchTable &t : g_batches) {
-        if (t.device == device) bt = &t;
+        if (t.device == device && t.stream == st) bt = &t;
     }
     if (!bt) {
         g_batches.emplace_back();
         bt = &g_batches.back();
         bt->device = device;
+        bt->stream = st;
     }
     std::vector<SysDesc> table;
     bool combine = false;
