@@ -70,3 +70,50 @@ def test_mode_mismatch_and_duplicates_rejected():
     assert e.value.status == nb.NB_E_INVAL
     a.close()
     b.close()
+
+
+def test_batches_on_two_streams_concurrently():
+    """Two threads step two different batches on two streams at once; each system ends bitwise
+    equal to the same system stepped alone (each stream has its own segment table)."""
+    import threading
+
+    import torch
+
+    nb = require_gpu()
+    print_case("two streams, two batches")
+    groups = [[(3000, 0.3, 11), (5000, 0.7, 12)], [(2048, 0.5, 13), (4096, 0.9, 14)]]
+    alone = []
+    for grp in groups:
+        for n, q, seed in grp:
+            s = nb.System.from_ic(synth.make_binary(n, q, seed=seed), mode="kahan")
+            s.step(12)
+            alone.append((s.positions(), s.velocities()))
+            s.close()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    mixes = []
+    for grp, st in zip(groups, streams):
+        mixes.append([nb.System.from_ic(synth.make_binary(n, q, seed=seed), mode="kahan",
+                                        stream=st) for n, q, seed in grp])
+    torch.cuda.synchronize()
+    errors = []
+
+    def run(mix, st):
+        try:
+            for _ in range(12):
+                nb.step_many(mix, 1, st)
+        except Exception as e:  # surfaced below
+            errors.append(e)
+
+    threads = [threading.Thread(target=run, args=(m, st)) for m, st in zip(mixes, streams)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors
+    got = [(s.positions(), s.velocities()) for m in mixes for s in m]
+    for (xa, va), (xb, vb) in zip(alone, got):
+        assert np.array_equal(xa, xb)
+        assert np.array_equal(va, vb)
+    for m in mixes:
+        for s in m:
+            s.close()
