@@ -2,17 +2,23 @@
 //
 // The O(N^2) all-pairs force evaluation (Methodology: every element moves only under the sum of
 // all pairwise element-element interactions) is the hot path. It runs on the FP32 vector ALUs:
-// the pair sum is not a dense contraction, so there is no MFMA here. Each lane keeps KI i
-// elements in registers, the block streams j elements through LDS in 256-element SoA tiles
-// (coalesced global loads, double-buffered, one barrier per tile) and each wave reads a tile
-// back with broadcast ds_read_b128. Per pair:
+// the pair sum is not a dense contraction, so there is no MFMA here. Three kernels evaluate it:
+//   - k_force_sym (FP32, Kahan mode, the default): each unordered pair once, i in registers and
+//     the j sums rotating across the wave (see the section below), for both element laws;
+//   - k_force_f32 (FP32, plain mode): one-sided, each lane keeps KI i elements and the block
+//     streams 256-element SoA j tiles through LDS (broadcast ds_read_b128), one FP32 running sum;
+//   - k_force_f64 (FP64 reference mode): one-sided, both element laws.
+// All of them work on a Morton-sorted, star-by-star padded copy of the positions; the FP32 ones
+// skip the contact test on tiles whose bounding boxes are at least D apart. Per pair of the
+// contact law:
 //   d = r_j - r_i,  r2 = d.d + eps,  w = rsqrt(r2)  (v_rsq_f32),
 //   s = min(w^3, c1 - c2 w),  acc += s d,
 // where c1 = 11 / D^3 and c2 = 10 / D^2 for the pair's diameter D. Dividing the contact law
 // f(r) = G m^2 / r^2 (r >= D), G m^2 r / D^3 - K (1 - r/D) (r < D, K = 10 G m^2 / D^2) by
 // G m^2 r gives w^3 outside and c1 - c2 w inside; with x = r/D, 11 - 10/x - 1/x^3 is increasing
 // and vanishes at x = 1, so the smaller of the two expressions is always the right branch.
-// The self pair has d = 0 exactly and contributes 0; eps = 1e-24 keeps its w finite.
+// The self pair has d = 0 exactly and contributes 0; eps = 1e-24 keeps its w finite. The law of
+// eqs. (4)-(6) is written out at pair_s.
 //
 // The remaining kernels are O(N): leap-frog kicks and drift, per-star centres of mass, the
 // donor growth update (eq. 3), the L1-plane count and the FP64 diagnostics. Every reduction runs
@@ -178,7 +184,7 @@ __global__ __launch_bounds__(BT) void k_gather(Launch L)
     }
 }
 
-// ------------------------------------------------------------------ FP32 force kernel
+// ------------------------------------------------------------------ FP32 one-sided force kernel
 
 template <int KI>
 struct IState {
@@ -397,16 +403,16 @@ __global__ __launch_bounds__(BT) NB_FORCE_ATTR void k_force_f32(Launch L)
 // ------------------------------------------------------------------ FP32 symmetric force kernel
 //
 // Newton's third law halves the pair work: the pair (i, j) with i in tile I and j in a later tile
-// J > I is evaluated once. Row I of the work is the block's 256 i slots against tiles I .. T-1,
+// J > I is evaluated once. Row I of the work is the 256 i slots of tile I against tiles I .. T-1,
 // cut into chunks of `ch` tiles. Within a wave each lane keeps one i element; a tile's 256 j
 // elements are taken as four groups of 64. At step s (0..63) lane l meets element (l - s) mod 64
 // of each group: its position is read from LDS at that rotating offset, and the j accumulator
 // travels with it, moved one lane per step by a DPP wave rotation fused into the update
 // a_j <- rotate(a_j) - s (r_j - r_i). After 64 steps (and one last rotation) every lane holds the
-// summed reaction of the wave's 64 i elements on its own j. The four waves' sums are added in
-// wave order and stored as the reaction of row I on those j. The diagonal tile J = I is
+// summed reaction of the wave's 64 i elements on its own j. The waves' sums are added in wave
+// order and stored as the reaction of the row (group) on those j. The diagonal tile J = I is
 // evaluated one-sided. k_combine_sym adds, per element, its own row's chunk partials and then
-// the reactions of every lower row, in that order, with Kahan compensation.
+// the reactions of every earlier row group, in that order, with Kahan compensation.
 
 constexpr int DPP_WAVE_ROR1 = 0x13C;  // lane l receives lane l - 1 (mod 64)
 
