@@ -142,9 +142,10 @@ int nb_step(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *stream)
 
 /* Captures n_steps steps of the listed systems (exactly the work nb_step would queue for them)
  * into a HIP graph with its own copy of the segment table, for replay with nb_graph_launch. The
- * capture runs on a private stream after `stream` has been synchronised; nothing executes. The
- * graph refers to the systems' buffers: it must be destroyed before any of them is. Force-kernel
- * timing (nb_timing_*) does not cover graph replays. */
+ * table upload and the capture run on a private stream: nothing executes and nothing is queued
+ * on `stream` (kept for symmetry with the other calls), so work already queued anywhere keeps
+ * running. The graph refers to the systems' buffers: it must be destroyed before any of them
+ * is. Force-kernel timing (nb_timing_*) does not cover graph replays. */
 int nb_graph_create(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *stream,
                     nb_graph **out);
 

@@ -711,24 +711,26 @@ int nb_graph_create(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void 
     if (!g) return NB_E_NOMEM;
     g->n_sys = n_sys;
     g->n_steps = n_steps;
-    hipStream_t st = static_cast<hipStream_t>(stream);
+    (void)stream;  // nothing is queued on the caller's stream
     hipStream_t cs = nullptr;
     int rc = NB_OK;
     do {
-        if (hipMalloc(&g->d_table, table.size() * sizeof(SysDesc)) != hipSuccess) {
-            g->d_table = nullptr;
-            rc = NB_E_NOMEM;
-            break;
-        }
-        if (hipMemcpyAsync(g->d_table, table.data(), table.size() * sizeof(SysDesc),
-                           hipMemcpyHostToDevice, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess) { rc = NB_E_HIP; break; }
-        L.sys = g->d_table;
         if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
             cs = nullptr;
             rc = NB_E_HIP;
             break;
         }
+        if (hipMalloc(&g->d_table, table.size() * sizeof(SysDesc)) != hipSuccess) {
+            g->d_table = nullptr;
+            rc = NB_E_NOMEM;
+            break;
+        }
+        // the table travels on the private stream, so work already queued elsewhere keeps
+        // running while the graph is built
+        if (hipMemcpyAsync(g->d_table, table.data(), table.size() * sizeof(SysDesc),
+                           hipMemcpyHostToDevice, cs) != hipSuccess ||
+            hipStreamSynchronize(cs) != hipSuccess) { rc = NB_E_HIP; break; }
+        L.sys = g->d_table;
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             rc = NB_E_HIP;
             break;

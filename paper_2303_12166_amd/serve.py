@@ -8,6 +8,11 @@ requests first-come first-served while their device footprint fits the memory bu
 newly admitted systems on a second stream in a worker thread, so admission overlaps the running
 rounds. A request whose footprint exceeds the whole budget is rejected.
 
+Rounds are queued ``depth`` (default 2) ahead on the compute stream: while one round runs, the
+host picks the next round's systems, builds its graph if needed and queues it, and only then waits
+for the older round to retire the systems it finished (their final state is copied on a separate
+stream after that round's event), so the GPU does not idle during the host's bookkeeping.
+
 Which admitted systems take part in a round is a policy choice. ``"all"`` steps every resident
 system each round (processor sharing: all requests finish together). ``"srpt"`` (default) orders
 the resident systems by remaining work (steps left times N^2) and takes the shortest ones until
@@ -70,11 +75,25 @@ def footprint_bytes(n: int, q: float, mode: str = "kahan") -> int:
     return 9 * max(n, 1) * elem + max(n, 1) + nb_scratch_bytes(p) + 256
 
 
-def state_digest(system: System) -> str:
+def state_digest(system: System, stream=None, after=None) -> str:
+    """Hash of the final positions and velocities. With ``stream`` the copies run there, after
+    ``after`` (an event) when given, and only that stream is waited for."""
+    import torch
+
     h = hashlib.sha256()
-    system.synchronize()
-    for t in (system.x, system.y, system.z, system.vx, system.vy, system.vz):
-        h.update(t[: system.n].cpu().numpy().tobytes())
+    if stream is None:
+        system.synchronize()
+        for t in (system.x, system.y, system.z, system.vx, system.vy, system.vz):
+            h.update(t[: system.n].cpu().numpy().tobytes())
+        return h.hexdigest()[:32]
+    with torch.cuda.stream(stream):
+        if after is not None:
+            stream.wait_event(after)
+        host = [t[: system.n].to("cpu", non_blocking=True) for t in
+                (system.x, system.y, system.z, system.vx, system.vy, system.vz)]
+        stream.synchronize()
+    for t in host:
+        h.update(t.numpy().tobytes())
     return h.hexdigest()[:32]
 
 
@@ -109,7 +128,7 @@ class BatchServer:
     def __init__(self, budget_bytes: int, round_steps: int = 10, max_active: int = 512,
                  mode: str = "kahan", dt: float = 1e-4, use_graphs: bool = True,
                  keep_digests: bool = True, policy: str = "srpt", fill: float = 1.2e10,
-                 workers: int = 2):
+                 workers: int = 2, depth: int = 2):
         if policy not in ("srpt", "all"):
             raise ValueError("policy must be 'srpt' or 'all'")
         import torch
@@ -125,7 +144,9 @@ class BatchServer:
         self.policy = policy
         self.fill = float(fill)
         self.workers = max(1, int(workers))
+        self.depth = max(1, int(depth))
         self.compute = torch.cuda.Stream()
+        self.copy_stream = torch.cuda.Stream()
         self.admit_stream = torch.cuda.Stream()
         self.rounds = 0
         self.graphs_built = 0
@@ -156,7 +177,8 @@ class BatchServer:
                    for _ in range(self.workers)]
         for w in workers:
             w.start()
-        active = []  # [System, Record, remaining]
+        active = []  # [System, Record, steps not yet queued]
+        inflight = collections.deque()  # queued rounds: (event, systems it finishes, graph key)
         reserved = 0
         in_flight = 0
         graphs = {}  # (request ids of the round's systems, k) -> graph
@@ -166,7 +188,7 @@ class BatchServer:
             return time.perf_counter() - t0
 
         try:
-            while pending or waiting or active or in_flight:
+            while pending or waiting or active or in_flight or inflight:
                 t = now()
                 while pending and pending[0].t_arrive <= t:
                     req = pending.popleft()
@@ -194,7 +216,7 @@ class BatchServer:
                     if err is not None:
                         raise err
                     active.append([sysm, rec, req.steps])
-                if not active:
+                if not active and not inflight:
                     # idle: wait for an arrival or a system under construction
                     nxt = pending[0].t_arrive - now() if pending else 0.002
                     if in_flight:
@@ -206,48 +228,61 @@ class BatchServer:
                     elif nxt > 0:
                         time.sleep(min(nxt, 0.05))
                     continue
-                if self.policy == "srpt":
-                    order = sorted(active, key=lambda a: (a[2] * float(a[1].n) ** 2,
-                                                          a[1].t_arrive, a[1].rid))
-                    chosen, work = [], 0.0
-                    for a in order:
-                        chosen.append(a)
-                        work += float(a[1].n) ** 2
-                        if work >= self.fill:
-                            break
-                else:
-                    chosen = active
-                k = min(self.round_steps, min(a[2] for a in chosen))
-                key = (tuple(a[1].rid for a in chosen), k)
-                if self.use_graphs:
-                    graph = graphs.get(key)
-                    if graph is None:
-                        graph = nb_graph_create([a[0].handle for a in chosen], k, self.compute)
-                        graphs[key] = graph
-                        self.graphs_built += 1
-                    nb_graph_launch(graph, self.compute)
-                else:
-                    from . import nb_step
+                # systems with steps left that no queued round will finish
+                open_ = [a for a in active if a[2] > 0]
+                if open_ and len(inflight) < self.depth:
+                    if self.policy == "srpt":
+                        order = sorted(open_, key=lambda a: (a[2] * float(a[1].n) ** 2,
+                                                             a[1].t_arrive, a[1].rid))
+                        chosen, work = [], 0.0
+                        for a in order:
+                            chosen.append(a)
+                            work += float(a[1].n) ** 2
+                            if work >= self.fill:
+                                break
+                    else:
+                        chosen = open_
+                    k = min(self.round_steps, min(a[2] for a in chosen))
+                    key = (tuple(a[1].rid for a in chosen), k)
+                    if self.use_graphs:
+                        graph = graphs.get(key)
+                        if graph is None:
+                            graph = nb_graph_create([a[0].handle for a in chosen], k,
+                                                    self.compute)
+                            graphs[key] = graph
+                            self.graphs_built += 1
+                        nb_graph_launch(graph, self.compute)
+                    else:
+                        from . import nb_step
 
-                    nb_step([a[0].handle for a in chosen], k, self.compute)
-                self.compute.synchronize()
-                self.rounds += 1
+                        nb_step([a[0].handle for a in chosen], k, self.compute)
+                    ev = self.torch.cuda.Event()
+                    ev.record(self.compute)
+                    self.rounds += 1
+                    finishing = []
+                    for a in chosen:
+                        a[2] -= k
+                        if a[2] <= 0:
+                            finishing.append(a)
+                    inflight.append((ev, finishing, key))
+                    continue
+                if not inflight:
+                    continue
+                # the oldest queued round: wait for it, then retire the systems it finished
+                ev, finishing, _ = inflight.popleft()
+                ev.synchronize()
                 t = now()
-                retired = []
-                for a in chosen:
-                    a[2] -= k
-                    if a[2] <= 0:
+                if finishing:
+                    for a in finishing:
                         sysm, rec = a[0], a[1]
                         rec.t_done = t
                         rec.status = "done"
                         if self.keep_digests:
-                            rec.digest = state_digest(sysm)
-                        retired.append(a)
-                if retired:
-                    gone = {a[1].rid for a in retired}
+                            rec.digest = state_digest(sysm, self.copy_stream, ev)
+                    gone = {a[1].rid for a in finishing}
                     for gk in [gk for gk in graphs if gone.intersection(gk[0])]:
                         nb_graph_destroy(graphs.pop(gk))
-                    for a in retired:
+                    for a in finishing:
                         reserved -= a[1].bytes
                         a[0].close()
                     active = [a for a in active if a[1].rid not in gone]
@@ -255,9 +290,10 @@ class BatchServer:
                         log("t=%.2fs active=%d waiting=%d done=%d" % (
                             t, len(active), len(waiting),
                             sum(r.status == "done" for r in recs.values())))
-                if len(graphs) > 64:  # bound the cache: drop graphs of older rounds
+                if len(graphs) > 64:  # bound the cache: drop graphs no queued round uses
+                    busy = {q[2] for q in inflight}
                     for gk in list(graphs)[:-16]:
-                        if gk != key:
+                        if gk not in busy:
                             nb_graph_destroy(graphs.pop(gk))
         finally:
             for _ in workers:
