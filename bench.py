@@ -55,9 +55,9 @@ def kernel_source_sha() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def counter_record(workload: str, mode: str):
+def counter_record(workload: str, mode: str, nsplit: int):
     """The committed rocprofv3 counter record of this workload's force kernel, if it was taken
-    with this kernel source (HBM bytes per launch, VALU instructions per pair)."""
+    with this kernel source and work split (HBM bytes per launch, VALU instructions per pair)."""
     try:
         with open(COUNTERS_FILE) as f:
             rec = json.load(f)
@@ -65,6 +65,8 @@ def counter_record(workload: str, mode: str):
         return None
     entry = rec.get("%s:%s" % (workload, mode))
     if not entry or entry.get("kernel_sha") != kernel_source_sha():
+        return None
+    if entry.get("nsplit") != nsplit:
         return None
     return entry
 
@@ -441,7 +443,7 @@ def main() -> int:
     value = inter * steps / elapsed
     avg_s = force_ms / max(launches, 1) / 1e3
     peak = PEAK_FP64_TFLOPS if mode == "fp64" else PEAK_FP32_TFLOPS
-    counters = counter_record(args.workload + (":paper" if law else ""), mode)
+    counters = counter_record(args.workload + (":paper" if law else ""), mode, cfg["nsplit"])
     achieved = FLOPS_PER_INTERACTION * inter / avg_s / 1e12 if avg_s > 0 else 0.0
     roofline = {
         "bound": "alu",

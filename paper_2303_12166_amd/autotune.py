@@ -1,12 +1,12 @@
-"""Autotuner for the force kernel's work split.
+"""Autotuner for the force kernels' work split.
 
-The kernel's compile-time shape (one i element per lane, 256-element j tiles, two groups of four
-j per unrolled step, eight waves per SIMD) was fixed by measurement. What depends on the system
-size is how many j chunks each i-block is split into: more chunks mean more, shorter work units
-(better balance, more partial sums to combine). For each size bucket the tuner times every
-candidate split on a seeded two-star system and keeps the fastest; ``apply`` installs the table
-through ``nb_tile_override``, so the choice stays a function of the system size alone (a system
-gets the same split alone and in a batch).
+The kernels' compile-time shapes (tile sizes, waves per SIMD) were fixed by measurement. What
+depends on the system size is how many j chunks the work is split into: more chunks mean more,
+shorter work units (better balance across the 256 CUs, more partial sums to combine). For each
+size bucket the tuner times one whole force evaluation (gather, force kernel and combine) for
+every candidate split on a seeded two-star system and keeps the fastest; ``apply`` installs the
+table through ``nb_tile_override``, so the choice stays a function of the system size alone (a
+system gets the same split alone and in a batch).
 
     python -m paper_2303_12166_amd.autotune [--out FILE]     # on a GPU
 """
@@ -19,15 +19,14 @@ import math
 import os
 import sys
 
-from . import MODES, nb_tile_config, nb_tile_override, nb_timing_enable, nb_timing_read
-from . import nb_timing_reset, nb_version
+from . import MODES, nb_tile_config, nb_tile_override, nb_version
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE_PATH = os.path.join(HERE, "tuning", "gfx950.json")
 
 # bucket edges (inclusive ranges) covering 4096 .. 524288 elements, factor 2 apart
 EDGES = [4096, 8192, 16384, 32768, 65536, 131072, 262144, 524288]
-CANDIDATES = (1, 2, 4, 8, 16, 32, 64, 128, 256)
+CANDIDATES = (1, 2, 4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256)
 
 
 def buckets():
@@ -66,20 +65,24 @@ def apply_saved(path: str = TABLE_PATH) -> bool:
 
 
 def _time_forces(ic, mode: str, repeats: int) -> float:
+    """Mean time of one whole force evaluation (gather, force kernel and combine), from events
+    on the system's stream."""
+    import torch
+
     from .system import System
 
     s = System.from_ic(ic, mode=mode)
     s.forces()
     s.synchronize()
-    nb_timing_reset()
-    nb_timing_enable(True)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s.stream)
     for _ in range(repeats):
         s.forces()
-    s.synchronize()
-    nb_timing_enable(False)
-    ms, cnt = nb_timing_read()
+    b.record(s.stream)
+    b.synchronize()
+    ms = a.elapsed_time(b)
     s.close()
-    return ms / max(cnt, 1)
+    return ms / max(repeats, 1)
 
 
 def tune(mode: str = "kahan", q: float = 0.5, repeats: int = 4, max_n: int = 262144,
@@ -95,13 +98,16 @@ def tune(mode: str = "kahan", q: float = 0.5, repeats: int = 4, max_n: int = 262
         if lo > max_n:
             break
         ic = synth.make_binary(n, q, seed=7)
-        timings = {}
+        timings, seen = {}, set()
         for ns in CANDIDATES:
             nb_tile_override(n, n, ns)
             try:
                 cfg = nb_tile_config(n, ic.n1, MODES[mode])
-                if cfg["nsplit"] != ns:
-                    continue  # more chunks than tiles
+                # requests that give the same work split as an earlier one are skipped
+                split = (cfg["nsplit"], cfg["jchunk"])
+                if split in seen or cfg["nsplit"] > ns:
+                    continue
+                seen.add(split)
                 timings[ns] = _time_forces(ic, mode, repeats)
             finally:
                 nb_tile_override(n, n, 0)
