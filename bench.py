@@ -32,6 +32,7 @@ FLOPS_PER_INTERACTION = 20
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 (packed FP32) x 2 (FMA) x 2.4 GHz
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
+VALU_LANE_ISSUE_PER_S = 256 * 128 * 2.4e9  # non-packed VALU lane-instructions per second
 
 WORKLOADS = {
     "c3": dict(n=262144, q=0.3, mode="kahan", steps=200, warmup=5),
@@ -460,13 +461,22 @@ def main() -> int:
         "kernel_interactions_per_s": inter / avg_s if avg_s > 0 else 0.0,
     }
     if counters:
+        # pairs the kernel evaluates: N^2 / 2 with the symmetric kernel, N^2 one-sided
+        evaluated = inter / 2 if roofline["kernel"].startswith("k_force_sym") else inter
+        vpp = counters.get("valu_lane_instructions_per_pair")
         roofline["counters"] = {
-            "source": "profiles/force_counters.json (rocprofv3, same kernel source)",
-            "valu_lane_instructions_per_pair": counters.get("valu_lane_instructions_per_pair"),
+            "source": "profiles/force_counters.json (rocprofv3, same kernel source and split)",
+            "valu_lane_instructions_per_pair": vpp,
             "trans_lane_instructions_per_pair": counters.get("trans_lane_instructions_per_pair"),
             "hbm_bytes_per_launch": counters.get("bytes_per_launch"),
             "algorithmic_bytes_per_launch": counters.get("algorithmic_bytes_per_launch"),
         }
+        if vpp and avg_s > 0:
+            # achieved VALU issue (all VALU instructions, live timing) against the non-packed
+            # issue rate of 256 CUs x 128 lanes per clock x 2.4 GHz
+            rate = vpp * evaluated / avg_s
+            roofline["counters"]["valu_lane_instructions_per_s"] = rate
+            roofline["counters"]["valu_issue_frac"] = round(rate / VALU_LANE_ISSUE_PER_S, 4)
 
     out = {
         "metric": METRIC,
