@@ -5,12 +5,13 @@
  *
  * The model (Methodology section): a star is a ball of N elements of one common mass and one
  * common diameter; every element's motion comes only from the sum of all pairwise
- * element-element interactions. Elements always attract; elements in contact also repel. The
- * contact law implemented here is the conservative one
+ * element-element interactions. Elements always attract; elements in contact also repel. Two
+ * element laws are implemented (nb_params.law). The default is a conservative contact law
  *     f(r) = G m^2 / r^2                       r >= D
  *     f(r) = G m^2 r / D^3 - K (1 - r/D)       r <  D,   K = 10 G m^2 / D^2
  * (f > 0 attracts), with D the element diameter of the pair: D1 inside star 1, D2 inside star 2,
- * (D1 + D2)/2 across. Time stepping is the leap-frog integrator (Methodology) in kick-drift-kick
+ * (D1 + D2)/2 across; the other is the paper's own law, eqs. (4)-(6), described at nb_params.
+ * Time stepping is the leap-frog integrator (Methodology) in kick-drift-kick
  * form. The donor (star 2) expands by growing its element diameter until its radius reaches the
  * Roche-lobe radius of eq. (3); elements of the donor crossing the plane through L1 are counted
  * every step.
@@ -45,7 +46,8 @@ extern "C" {
 #define NB_E_HIP (-2)       /* a HIP runtime call failed */
 #define NB_E_NOMEM (-3)     /* scratch smaller than nb_scratch_bytes, or a library table failed */
 #define NB_E_NONFINITE (-4) /* a position or velocity became NaN or infinite */
-#define NB_E_MISMATCH (-5)  /* systems of different precision modes in one multi-system call */
+#define NB_E_MISMATCH (-5)  /* systems of different precision modes or element laws in one
+                               multi-system call */
 
 /* element laws */
 #define NB_LAW_CONTACT 0 /* conservative contact law (default; see the header comment) */
@@ -112,8 +114,9 @@ typedef struct {
     int32_t pad;
 } nb_diag;
 
-/* Bytes of device workspace (`scratch`) a system with these parameters needs. Depends only on
- * n, n1 and mode. Returns NB_E_INVAL for invalid parameters. */
+/* Bytes of device workspace (`scratch`) a system with these parameters needs. Depends on n, n1,
+ * mode and law, and on the work split installed for n (nb_tile_override). Returns NB_E_INVAL for
+ * invalid parameters. */
 int nb_scratch_bytes(const nb_params *p, size_t *out);
 
 /* Validates p and b, lays out the workspace, initialises the device state (FP64 diameters and
@@ -185,7 +188,8 @@ int nb_timing_read(double *total_ms, int64_t *launches);
 int nb_timing_reset(void);
 
 /* Work split chosen for a system of n elements (n1 in star 1) in a mode: i elements per lane
- * (ki), j chunks per i-block (nsplit), i-block size and chunk length (in sorted slots). The
+ * (ki), j chunks per i-block (nsplit; for the symmetric FP32 Kahan kernel, the chunk count of
+ * the longest tile row), i-block size and chunk length (in sorted slots). The
  * force kernels work on a copy of the positions sorted per star (Morton order of the initial
  * positions, each star padded to a multiple of 256 slots); results are returned in element
  * order. Depends only on (n, n1, mode) and the overrides below. Any output pointer may be NULL. */
