@@ -1,0 +1,29 @@
+"""CPU checks of bench.py's command-line contract (no GPU needed)."""
+
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_counter_record_requires_matching_source_and_split():
+    sys.path.insert(0, ROOT)
+    import bench
+
+    with open(bench.COUNTERS_FILE) as f:
+        rec = json.load(f)
+    entry = rec["c3:kahan"]
+    if entry["kernel_sha"] == bench.kernel_source_sha():
+        assert bench.counter_record("c3", "kahan", entry["nsplit"]) == entry
+    assert bench.counter_record("c3", "kahan", entry["nsplit"] + 1) is None
+    assert bench.counter_record("c3", "nonexistent-mode", entry["nsplit"]) is None
