@@ -134,7 +134,7 @@ int nb_forces(nb_system *s, void *stream);
 /* Advances every listed system by n_steps leap-frog steps (Methodology: leap-frog integrator):
  * v += a dt/2; x += v dt; a = F(x); v += a dt/2; then the donor growth update (diameter grows by
  * (1 + growth_rate) while R2_0 D2/D2_0 <= r_L(q) a, eq. 3; the first step that finds it larger
- * stops growth for good) and the L1 count. n_sys = 1 is the plain path. With n_sys > 1 all
+ * stops growth for good) and the L1 count. n_sys = 1 steps one system alone. With n_sys > 1 all
  * systems advance together: each kernel of a step is one launch over all systems' work (a
  * segment table), and each system's results are bitwise the same as when it runs alone. The
  * systems must be distinct (NB_E_INVAL) and share one mode and one element law (NB_E_MISMATCH).

@@ -19,8 +19,9 @@ the resident systems by remaining work (steps left times N^2) and takes the shor
 the round's per-step work reaches ``fill`` pair interactions, enough to keep the GPU busy, so short
 requests finish first while large ones still fill the machine.
 
-The one-at-a-time baseline runs the same trace through the plain path: each request, in arrival
-order, is created and stepped alone to completion before the next one starts.
+The one-at-a-time baseline runs the same trace through the single-system path (nb_step with one
+system, same precision mode): each request, in arrival order, is created and stepped alone to
+completion before the next one starts.
 
 Each system's kernels, work split and reduction orders depend on its own size only, so its result
 is bitwise the same alone and in any mix; both runs record a digest of every final state.
@@ -310,7 +311,7 @@ class BatchServer:
 
 def run_sequential(trace, mode: str = "kahan", dt: float = 1e-4, chunk: int = 100,
                    keep_digests: bool = True, log=None) -> list:
-    """One system at a time, in arrival order, each stepped alone to completion (plain path)."""
+    """One system at a time, in arrival order, each stepped alone to completion."""
     import torch
 
     stream = torch.cuda.Stream()
