@@ -506,6 +506,11 @@ def main() -> int:
         "roofline": roofline,
         "state_after": {"step": d["step"], "n_past_L1": d["n_past_L1"], "D2": d["D2"],
                         "nonfinite": d["nonfinite"]},
+        # the paper measures nothing on this path; its one performance figure is a vendor peak
+        "paper_context": {"hardware": "NVIDIA GeForce RTX 3080", "vendor_fp32_peak_tflops": 29.0,
+                          "measured": None,
+                          "note": "quoted in the paper's Methodology section as the GPU's "
+                                  "processing power; no timing, N or throughput is reported"},
     }
     s.close()
 
