@@ -381,7 +381,7 @@ const char *nb_strerror(int status)
     case NB_E_HIP: return "HIP runtime error";
     case NB_E_NOMEM: return "workspace too small or table allocation failed";
     case NB_E_NONFINITE: return "non-finite position or velocity";
-    case NB_E_MISMATCH: return "systems of different modes in one call";
+    case NB_E_MISMATCH: return "systems of different modes or element laws in one call";
     default: return "unknown status";
     }
 }
