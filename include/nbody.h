@@ -44,7 +44,8 @@ extern "C" {
 #define NB_OK 0
 #define NB_E_INVAL (-1)     /* bad argument: null pointer, size, mode, misaligned buffer */
 #define NB_E_HIP (-2)       /* a HIP runtime call failed */
-#define NB_E_NOMEM (-3)     /* scratch smaller than nb_scratch_bytes, or a library table failed */
+#define NB_E_NOMEM (-3)     /* scratch smaller than nb_scratch_bytes, a library table failed, or
+                               the work split of a huge system would overflow int32 units */
 #define NB_E_NONFINITE (-4) /* a position or velocity became NaN or infinite */
 #define NB_E_MISMATCH (-5)  /* systems of different precision modes or element laws in one
                                multi-system call */
@@ -64,7 +65,7 @@ typedef struct nb_graph nb_graph;   /* opaque: a captured multi-step launch sequ
 
 /* Physical and numerical parameters of one two-star system. */
 typedef struct {
-    int64_t n;           /* elements, 0 <= n < 2^31 */
+    int64_t n;           /* elements, 0 <= n < 2^30 */
     int64_t n1;          /* elements of star 1, 0 <= n1 <= n */
     double G;            /* gravitational constant */
     double m;            /* common element mass */

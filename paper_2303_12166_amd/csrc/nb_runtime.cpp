@@ -98,14 +98,17 @@ TileCfg tile_config(int64_t n, int64_t n1, int mode)
             units += (span + c.ch - 1) / c.ch;
             react_tiles += span - 1;
         }
-        c.n_units = (int)units;
+        // far beyond any device's memory the unit count no longer fits int32: n_units = -1
+        // makes nb_scratch_bytes and nb_create report NB_E_NOMEM
+        c.n_units = units > INT32_MAX ? -1 : (int)units;
         c.react_floats = (size_t)3 * TJ * (size_t)react_tiles;
         return c;
     }
     // chunk c covers tiles [c ntiles / nsplit, (c + 1) ntiles / nsplit)
     c.nsplit = c.ntiles > 0 ? std::max(1, std::min(ns, c.ntiles)) : 1;
     c.jchunk = c.ntiles > 0 ? (c.ntiles + c.nsplit - 1) / c.nsplit * TJ : TJ;
-    c.n_units = c.n_iblocks * c.nsplit;
+    const int64_t units = (int64_t)c.n_iblocks * c.nsplit;
+    c.n_units = units > INT32_MAX ? -1 : (int)units;
     return c;
 }
 
@@ -196,7 +199,8 @@ void morton_order(const T *x, const T *y, const T *z, int64_t b, int64_t e,
 bool params_ok(const nb_params *p)
 {
     if (!p) return false;
-    if (p->n < 0 || p->n >= (int64_t(1) << 31)) return false;
+    // n < 2^30 keeps every padded slot count and slot index inside int32
+    if (p->n < 0 || p->n >= (int64_t(1) << 30)) return false;
     if (p->n1 < 0 || p->n1 > p->n) return false;
     if (p->mode != NB_FP32_PLAIN && p->mode != NB_FP32_KAHAN && p->mode != NB_FP64) return false;
     auto pos = [](double v) { return std::isfinite(v) && v > 0.0; };
@@ -379,7 +383,7 @@ const char *nb_strerror(int status)
     case NB_OK: return "ok";
     case NB_E_INVAL: return "invalid argument";
     case NB_E_HIP: return "HIP runtime error";
-    case NB_E_NOMEM: return "workspace too small or table allocation failed";
+    case NB_E_NOMEM: return "workspace too small, table allocation failed or system too large";
     case NB_E_NONFINITE: return "non-finite position or velocity";
     case NB_E_MISMATCH: return "systems of different modes or element laws in one call";
     default: return "unknown status";
@@ -389,7 +393,7 @@ const char *nb_strerror(int status)
 int nb_tile_config(int64_t n, int64_t n1, int32_t mode, int32_t *ki, int32_t *nsplit,
                    int32_t *iblock, int32_t *jchunk)
 {
-    if (n < 0 || n >= (int64_t(1) << 31) || n1 < 0 || n1 > n) return NB_E_INVAL;
+    if (n < 0 || n >= (int64_t(1) << 30) || n1 < 0 || n1 > n) return NB_E_INVAL;
     if (mode != NB_FP32_PLAIN && mode != NB_FP32_KAHAN && mode != NB_FP64) return NB_E_INVAL;
     TileCfg c = tile_config(n, n1, mode);
     if (ki) *ki = c.ki;
@@ -421,6 +425,7 @@ int nb_scratch_bytes(const nb_params *p, size_t *out)
 {
     if (!params_ok(p) || !out) return NB_E_INVAL;
     TileCfg c = tile_config(p->n, p->n1, p->mode);
+    if (c.n_units < 0) return NB_E_NOMEM;
     *out = layout_for(p->mode, p->law, c).total;
     return NB_OK;
 }
@@ -440,6 +445,7 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
     }
     if (!b->scratch || !aligned(b->scratch, ALIGN)) return NB_E_INVAL;
     TileCfg cfg = tile_config(p->n, p->n1, p->mode);
+    if (cfg.n_units < 0) return NB_E_NOMEM;
     Layout lay = layout_for(p->mode, p->law, cfg);
     if (b->scratch_bytes < lay.total) return NB_E_NOMEM;
 

@@ -91,7 +91,7 @@ def test_tile_override(nb):
 
 @pytest.mark.parametrize("bad", [dict(n=-1), dict(n1=3000), dict(mode=7), dict(D1=0.0),
                                  dict(m=float("nan")), dict(q=-0.5), dict(growth_rate=-1.0),
-                                 dict(n=1 << 31, n1=0), dict(law=5),
+                                 dict(n=1 << 31, n1=0), dict(n=1 << 30, n1=0), dict(law=5),
                                  dict(law=1, mode=0), dict(law=1, beta=1.5),
                                  dict(law=1, gamma=-1.0), dict(law=1, eps=-0.1),
                                  dict(law=1, G=0.0)])
@@ -154,3 +154,14 @@ def test_scratch_bytes_grow_by_sorted_velocities_under_the_paper_law(nb):
     b64 = _params(nb, mode=nb.NB_FP64)
     p64 = _params(nb, mode=nb.NB_FP64, law=nb.NB_LAW_PAPER, eps=0.001, gamma=1.0, beta=0.5)
     assert nb.nb_scratch_bytes(p64) - nb.nb_scratch_bytes(b64) == 3 * (-(-slots * 8 // 256) * 256)
+
+
+def test_huge_systems_report_nomem_instead_of_overflowing(nb):
+    """Near the 2^30 element limit the symmetric and FP64 work splits would need more than 2^31
+    units; the library reports NB_E_NOMEM rather than wrapping the count."""
+    big = dict(n=(1 << 30) - 1, n1=1 << 29)
+    assert nb.nb_scratch_bytes(_params(nb, mode=nb.NB_FP32_PLAIN, **big)) > 0
+    for mode in (nb.NB_FP32_KAHAN, nb.NB_FP64):
+        with pytest.raises(nb.NbError) as e:
+            nb.nb_scratch_bytes(_params(nb, mode=mode, **big))
+        assert e.value.status == nb.NB_E_NOMEM
