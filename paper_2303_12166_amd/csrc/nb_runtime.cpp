@@ -338,6 +338,7 @@ bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 int check_system_list(nb_system *const *sys, int32_t n_sys)
 {
     if (!sys || n_sys < 1) return NB_E_INVAL;
+    int64_t units = 0, ounits = 0, tiles = 0;
     for (int k = 0; k < n_sys; ++k) {
         if (!sys[k]) return NB_E_INVAL;
         if (sys[k]->p.mode != sys[0]->p.mode) return NB_E_MISMATCH;
@@ -345,7 +346,12 @@ int check_system_list(nb_system *const *sys, int32_t n_sys)
         for (int j = 0; j < k; ++j) {
             if (sys[j] == sys[k]) return NB_E_INVAL;
         }
+        units += sys[k]->cfg.n_units;
+        ounits += sys[k]->cfg.n_ounits;
+        tiles += sys[k]->cfg.ntiles;
     }
+    // the segment table's prefix offsets are int32
+    if (units > INT32_MAX || ounits > INT32_MAX || tiles > INT32_MAX) return NB_E_NOMEM;
     return NB_OK;
 }
 
