@@ -138,7 +138,8 @@ int nb_forces(nb_system *s, void *stream);
  * stops growth for good) and the L1 count. n_sys = 1 steps one system alone. With n_sys > 1 all
  * systems advance together: each kernel of a step is one launch over all systems' work (a
  * segment table), and each system's results are bitwise the same as when it runs alone. The
- * systems must be distinct (NB_E_INVAL) and share one mode and one element law (NB_E_MISMATCH).
+ * systems must be distinct (NB_E_INVAL) and share one mode and one element law (NB_E_MISMATCH);
+ * a batch whose summed work units, elements or tiles exceed int32 returns NB_E_NOMEM.
  * The library keeps the segment table of the last multi-system call per device and stream;
  * calls on one stream are ordered, calls on different streams do not share a table.
  * Asynchronous on `stream`. */
