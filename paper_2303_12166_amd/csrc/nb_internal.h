@@ -151,9 +151,10 @@ struct Launch {
 hipError_t launch_init_state(DevState *st, const DevState &init, hipStream_t s);
 hipError_t launch_fill_sorted(void *xs, void *ys, void *zs, int nalloc, int mode, bool sentinel,
                               hipStream_t s);
-hipError_t launch_gather(const Launch &L, int mode, bool drift, hipStream_t s);
+hipError_t launch_gather(const Launch &L, int mode, hipStream_t s);
 hipError_t launch_forces(const Launch &L, int mode, int max_blocks, hipStream_t s);
 hipError_t launch_combine(const Launch &L, int mode, hipStream_t s);
+hipError_t launch_kick_drift(const Launch &L, int mode, hipStream_t s);
 hipError_t launch_kick_stats(const Launch &L, int mode, int do_kick, hipStream_t s);
 hipError_t launch_finalize_step(const Launch &L, int do_growth, hipStream_t s);
 hipError_t launch_l1_classify(const Launch &L, int mode, int init, hipStream_t s);

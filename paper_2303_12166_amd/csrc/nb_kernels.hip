@@ -90,20 +90,6 @@ __device__ __forceinline__ int pair_class(int istar, int jstar) { return istar +
 
 constexpr double PI_D = 3.14159265358979323846;
 
-// Half step and step of the leap-frog in the state type.
-template <typename T>
-__device__ __forceinline__ T h_of(const DevState *st);
-template <>
-__device__ __forceinline__ float h_of<float>(const DevState *st) { return st->h_f; }
-template <>
-__device__ __forceinline__ double h_of<double>(const DevState *st) { return st->h_d; }
-template <typename T>
-__device__ __forceinline__ T dt_of(const DevState *st);
-template <>
-__device__ __forceinline__ float dt_of<float>(const DevState *st) { return st->dt_f; }
-template <>
-__device__ __forceinline__ double dt_of<double>(const DevState *st) { return st->dt; }
-
 // ------------------------------------------------------------------ sorted layout
 
 __device__ __forceinline__ int find_tile_sys(const Launch &L, int u)
@@ -147,10 +133,7 @@ __global__ __launch_bounds__(BT) void k_fill_sorted(T *xs, T *ys, T *zs, int nal
 
 // Pulls the current positions (and, under eqs. (4)-(6), velocities) into sorted order and records
 // each tile's bounding box (padding slots keep their fill values and are left out of the box).
-// With DRIFT the step's first kick and drift are applied on the way (v += a dt/2, then
-// x += v dt), each element once through its sorted slot, and the new x and v are written back as
-// well.
-template <typename T, bool DRIFT>
+template <typename T>
 __global__ __launch_bounds__(BT) void k_gather(Launch L)
 {
     __shared__ float lds[6][BT / 64];
@@ -162,36 +145,16 @@ __global__ __launch_bounds__(BT) void k_gather(Launch L)
         const int idx = S.perm[slot];
         float v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
         if (idx >= 0) {
-            T x = static_cast<const T *>(S.x)[idx];
-            T y = static_cast<const T *>(S.y)[idx];
-            T z = static_cast<const T *>(S.z)[idx];
-            T vx = static_cast<const T *>(S.vx)[idx];
-            T vy = static_cast<const T *>(S.vy)[idx];
-            T vz = static_cast<const T *>(S.vz)[idx];
-            if constexpr (DRIFT) {
-                const T h = h_of<T>(S.st), dt = dt_of<T>(S.st);
-                const T *ax = static_cast<const T *>(S.ax), *ay = static_cast<const T *>(S.ay),
-                        *az = static_cast<const T *>(S.az);
-                vx = vx + h * ax[idx];
-                vy = vy + h * ay[idx];
-                vz = vz + h * az[idx];
-                x = x + dt * vx;
-                y = y + dt * vy;
-                z = z + dt * vz;
-                static_cast<T *>(S.vx)[idx] = vx;
-                static_cast<T *>(S.vy)[idx] = vy;
-                static_cast<T *>(S.vz)[idx] = vz;
-                static_cast<T *>(S.x)[idx] = x;
-                static_cast<T *>(S.y)[idx] = y;
-                static_cast<T *>(S.z)[idx] = z;
-            }
+            const T x = static_cast<const T *>(S.x)[idx];
+            const T y = static_cast<const T *>(S.y)[idx];
+            const T z = static_cast<const T *>(S.z)[idx];
             static_cast<T *>(S.xs)[slot] = x;
             static_cast<T *>(S.ys)[slot] = y;
             static_cast<T *>(S.zs)[slot] = z;
             if (S.vxs) {
-                static_cast<T *>(S.vxs)[slot] = vx;
-                static_cast<T *>(S.vys)[slot] = vy;
-                static_cast<T *>(S.vzs)[slot] = vz;
+                static_cast<T *>(S.vxs)[slot] = static_cast<const T *>(S.vx)[idx];
+                static_cast<T *>(S.vys)[slot] = static_cast<const T *>(S.vy)[idx];
+                static_cast<T *>(S.vzs)[slot] = static_cast<const T *>(S.vz)[idx];
             }
             v[0] = v[3] = (float)x;
             v[1] = v[4] = (float)y;
@@ -1021,6 +984,42 @@ __global__ __launch_bounds__(BT) void k_combine(Launch L)
 
 // ------------------------------------------------------------------ leap-frog and L1 plane
 
+template <typename T>
+__device__ __forceinline__ T h_of(const DevState *st);
+template <>
+__device__ __forceinline__ float h_of<float>(const DevState *st) { return st->h_f; }
+template <>
+__device__ __forceinline__ double h_of<double>(const DevState *st) { return st->h_d; }
+template <typename T>
+__device__ __forceinline__ T dt_of(const DevState *st);
+template <>
+__device__ __forceinline__ float dt_of<float>(const DevState *st) { return st->dt_f; }
+template <>
+__device__ __forceinline__ double dt_of<double>(const DevState *st) { return st->dt; }
+
+// v += a dt/2; x += v dt
+template <typename T>
+__global__ __launch_bounds__(BT) void k_kick_drift(Launch L)
+{
+    for (int u = blockIdx.x; u < L.total_ounits; u += gridDim.x) {
+        const SysDesc &S = L.sys[find_sys(L, u, true)];
+        const int i = (u - S.ounit_begin) * BT + threadIdx.x;
+        if (i >= S.n) continue;
+        const T h = h_of<T>(S.st), dt = dt_of<T>(S.st);
+        T *x = static_cast<T *>(S.x), *y = static_cast<T *>(S.y), *z = static_cast<T *>(S.z);
+        T *vx = static_cast<T *>(S.vx), *vy = static_cast<T *>(S.vy), *vz = static_cast<T *>(S.vz);
+        const T *ax = static_cast<const T *>(S.ax), *ay = static_cast<const T *>(S.ay),
+                *az = static_cast<const T *>(S.az);
+        const T nvx = vx[i] + h * ax[i], nvy = vy[i] + h * ay[i], nvz = vz[i] + h * az[i];
+        vx[i] = nvx;
+        vy[i] = nvy;
+        vz[i] = nvz;
+        x[i] = x[i] + dt * nvx;
+        y[i] = y[i] + dt * nvy;
+        z[i] = z[i] + dt * nvz;
+    }
+}
+
 // Optional second kick v += a dt/2, then per-unit FP64 sums of each star's positions and the
 // count of non-finite elements.
 template <typename T>
@@ -1442,22 +1441,14 @@ hipError_t launch_fill_sorted(void *xs, void *ys, void *zs, int nalloc, int mode
     return hipGetLastError();
 }
 
-hipError_t launch_gather(const Launch &L, int mode, bool drift, hipStream_t s)
+hipError_t launch_gather(const Launch &L, int mode, hipStream_t s)
 {
     if (L.total_tunits == 0) return hipSuccess;
     const dim3 g(grid_for(L.total_tunits)), b(BT);
     if (mode == 2) {
-        if (drift) {
-            hipLaunchKernelGGL((k_gather<double, true>), g, b, 0, s, L);
-        } else {
-            hipLaunchKernelGGL((k_gather<double, false>), g, b, 0, s, L);
-        }
+        hipLaunchKernelGGL(k_gather<double>, g, b, 0, s, L);
     } else {
-        if (drift) {
-            hipLaunchKernelGGL((k_gather<float, true>), g, b, 0, s, L);
-        } else {
-            hipLaunchKernelGGL((k_gather<float, false>), g, b, 0, s, L);
-        }
+        hipLaunchKernelGGL(k_gather<float>, g, b, 0, s, L);
     }
     return hipGetLastError();
 }
@@ -1498,6 +1489,18 @@ hipError_t launch_combine(const Launch &L, int mode, hipStream_t s)
         hipLaunchKernelGGL(k_combine_sym<NB_COMBINE_SEGS>, g, dim3(BT * NB_COMBINE_SEGS), 0, s, L);
     } else {
         hipLaunchKernelGGL((k_combine<double, false>), g, b, 0, s, L);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_kick_drift(const Launch &L, int mode, hipStream_t s)
+{
+    if (L.total_ounits == 0) return hipSuccess;
+    const dim3 g(grid_for(L.total_ounits)), b(BT);
+    if (mode == 2) {
+        hipLaunchKernelGGL(k_kick_drift<double>, g, b, 0, s, L);
+    } else {
+        hipLaunchKernelGGL(k_kick_drift<float>, g, b, 0, s, L);
     }
     return hipGetLastError();
 }

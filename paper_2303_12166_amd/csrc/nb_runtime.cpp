@@ -279,12 +279,10 @@ int hip_status(hipError_t e) { return e == hipSuccess ? NB_OK : NB_E_HIP; }
         if (e_ != hipSuccess) return NB_E_HIP; \
     } while (0)
 
-// One force evaluation: gather (with drift = true also the step's first kick and drift), force
-// kernel, combine.
 int launch_force_timed(const Launch &L, int mode, hipStream_t st, bool need_combine,
-                       bool allow_timing = true, bool drift = false)
+                       bool allow_timing = true)
 {
-    NB_TRY(launch_gather(L, mode, drift, st));
+    NB_TRY(launch_gather(L, mode, st));
     hipEvent_t a = nullptr, b = nullptr;
     bool timed = false;
     if (allow_timing) {
@@ -310,8 +308,8 @@ int run_steps(const Launch &L, int mode, int n_steps, bool need_combine, hipStre
               bool allow_timing = true)
 {
     for (int k = 0; k < n_steps; ++k) {
-        // v += a dt/2 and x += v dt happen inside the gather of the step's force evaluation
-        int rc = launch_force_timed(L, mode, st, need_combine, allow_timing, true);
+        NB_TRY(launch_kick_drift(L, mode, st));
+        int rc = launch_force_timed(L, mode, st, need_combine, allow_timing);
         if (rc != NB_OK) return rc;
         NB_TRY(launch_kick_stats(L, mode, 1, st));
         NB_TRY(launch_finalize_step(L, 1, st));
@@ -628,7 +626,7 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
         if (launch_finalize_step(L, 0, st) != hipSuccess) { rc = NB_E_HIP; break; }
         if (launch_l1_classify(L, p->mode, 1, st) != hipSuccess) { rc = NB_E_HIP; break; }
         if (launch_finalize_l1(L, 1, st) != hipSuccess) { rc = NB_E_HIP; break; }
-        if (launch_gather(L, p->mode, false, st) != hipSuccess) { rc = NB_E_HIP; break; }
+        if (launch_gather(L, p->mode, st) != hipSuccess) { rc = NB_E_HIP; break; }
         if (launch_forces(L, p->mode, g_force_grid.load(), st) != hipSuccess) { rc = NB_E_HIP; break; }
         if ((cfg.nsplit > 1 || cfg.sym) && launch_combine(L, p->mode, st) != hipSuccess) {
             rc = NB_E_HIP;
