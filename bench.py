@@ -338,9 +338,12 @@ def main() -> int:
                          "(default 2000), step-0 force error vs the FP64 oracle and FP64 drift of "
                          "E, P and L (donor growth off so that the energy is conserved)")
     ap.add_argument("--lobe-fill", action="store_true",
-                    help="N=65536, q=0.5: grow the donor to its Roche lobe (about 4150 steps) and "
-                         "run --steps more after growth stops (default 2000); prints the binned "
-                         "L1 flux series and the accretor-side retention")
+                    help="grow the donor of an N=--lobe-n, q=--lobe-q system (default 65536, 0.5: "
+                         "about 4150 steps) to its Roche lobe and run --steps more after growth "
+                         "stops (default 2000); prints the binned L1 flux series and the "
+                         "accretor-side retention")
+    ap.add_argument("--lobe-n", type=int, default=65536, help="elements of the --lobe-fill run")
+    ap.add_argument("--lobe-q", type=float, default=0.5, help="mass ratio of the --lobe-fill run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (three times), the reference "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -365,7 +368,7 @@ def main() -> int:
 
         nb.load()
         torch.cuda.set_device(0)
-        res = lobe_fill(2000 if args.steps is None else args.steps)
+        res = lobe_fill(2000 if args.steps is None else args.steps, n=args.lobe_n, q=args.lobe_q)
         print(json.dumps({"metric": "lobe-filling run: L1 flux series and retention",
                           "value": None, "n_gpus": 1, "data": "synthetic", "lobe_fill": res}),
               flush=True)
