@@ -115,6 +115,8 @@ class System:
             t.record_stream(stream)
 
     # ------------------------------------------------------------ state read-back
+    # Read-backs wait for the system's own stream; work queued for it on another stream (for
+    # example a batch stepped on a server's compute stream) must be waited for by the caller.
 
     def _stack(self, a, b, c) -> np.ndarray:
         self.synchronize()
