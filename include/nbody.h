@@ -211,6 +211,7 @@ int nb_set_force_grid(int32_t blocks);
 
 void nb_destroy(nb_system *s);
 const char *nb_strerror(int status);
+/* ABI version: 3 (element laws in nb_params, nb_retention). */
 int nb_version(void);
 
 #ifdef __cplusplus

@@ -379,7 +379,7 @@ Launch build_table(nb_system *const *sys, int32_t n_sys, std::vector<SysDesc> &t
 
 extern "C" {
 
-int nb_version(void) { return 2; }
+int nb_version(void) { return 3; }
 
 const char *nb_strerror(int status)
 {
