@@ -119,6 +119,7 @@ def cpu_baseline(ic, target_seconds: float, law=None):
         "sample": "%d of %d rows, each against all %d elements (one FP64 force evaluation "
                   "of the step-0 state, %.1f s)" % (k, n, n, t),
         "cpu": cpu_model(),
+        "host_cpus_visible": os.cpu_count(),
         "detail": oracle_scaling(cores) if law is None else None,
     }, rows, ref
 
