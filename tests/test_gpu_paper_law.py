@@ -224,18 +224,19 @@ def test_mixed_laws_in_one_batch_are_rejected():
     b.close()
 
 
-def test_batched_paper_law_matches_alone():
+@pytest.mark.parametrize("mode", ["kahan", "fp64"])
+def test_batched_paper_law_matches_alone(mode):
     """Several law-1 systems stepped in one launch give the same bits as each stepped alone."""
     nb = require_gpu()
     ics = [noisy(n, q, seed=n) for n, q in ((700, 0.4), (1500, 0.9), (300, 0.2))]
-    print_case("paper law batch vs alone")
+    print_case("paper law batch vs alone", mode)
     alone = []
     for ic in ics:
-        s = nb.System.from_ic(ic, mode="kahan", **law_params(ic))
+        s = nb.System.from_ic(ic, mode=mode, **law_params(ic))
         s.step(5)
         alone.append((s.positions(), s.velocities()))
         s.close()
-    sys_ = [nb.System.from_ic(ic, mode="kahan", **law_params(ic)) for ic in ics]
+    sys_ = [nb.System.from_ic(ic, mode=mode, **law_params(ic)) for ic in ics]
     nb.nb_step([s.handle for s in sys_], 5, sys_[0].stream)
     for s, (x, v) in zip(sys_, alone):
         assert np.array_equal(s.positions(), x)
@@ -264,3 +265,26 @@ def test_graph_replays_match_nb_step(mode):
     assert np.array_equal(a.velocities(), b.velocities())
     a.close()
     b.close()
+
+
+def test_l1_counts_exact_under_the_paper_law():
+    """The L1 count does not depend on the law, but its inputs do: step by step, the GPU's count
+    and crossings equal the oracle's on the GPU's own state (integers decided in FP64 from the
+    same FP32 positions)."""
+    nb = require_gpu()
+    ic = synth.with_velocity_noise(synth.make_binary(6000, 0.5, seed=77, R2=0.55), 5.0, 1077)
+    kw = law_params(ic)
+    print_case("paper law L1 counts")
+    s = nb.System.from_ic(ic, mode="kahan", **kw)
+    side = np.zeros(ic.n, dtype=np.int8)
+    oracle.l1_count(s.positions().astype(np.float64), ic.n1, ic.q, side, init=True)
+    moved = 0
+    for k in range(25):
+        s.step(1)
+        expect = oracle.l1_count(s.positions().astype(np.float64), ic.n1, ic.q, side)
+        d = s.diagnostics()
+        assert (d["n_past_L1"], d["cross_fwd"], d["cross_bwd"]) == expect, k
+        moved += expect[1] + expect[2]
+    s.close()
+    print("paper law L1 crossings over 25 steps:", moved)
+    assert moved > 0
