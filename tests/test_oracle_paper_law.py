@@ -156,3 +156,35 @@ def test_split_run_equals_one_run(orc):
     assert np.array_equal(one.pos, split.pos)
     assert np.array_equal(one.vel, split.vel)
     assert np.array_equal(c_one, np.concatenate(parts))
+
+
+def test_force_in_a_step_sees_the_half_step_velocity(orc):
+    """Two overlapping elements closing slowly: the first half kick (strong repulsion) reverses
+    their relative velocity, so the force at the new positions must take the separating branch
+    (gamma beta), which only the half-step velocities show; with the start velocities it would
+    take the converging one. One step is written out here from the pinned pair scalar."""
+    R, G, m, eps, gamma, beta, dt = 0.05, 1.0, 0.01, 0.001, 2000.0, 0.2, 1e-3
+    x0 = np.array([[0.0, 0.0, 0.0], [0.06, 0.0, 0.0]])
+    v0 = np.array([[0.001, 0.0, 0.0], [-0.001, 0.0, 0.0]])  # converging, slowly
+
+    def accel(x, v):
+        d = x[1] - x[0]
+        r = np.linalg.norm(d)
+        vr = np.dot(v[1] - v[0], d) / r
+        f = orc.paper_force(r, vr, R, G, m, m, eps, gamma, beta)
+        a0 = (f / m) * d / r
+        return np.array([a0, -a0])
+
+    a = accel(x0, v0)
+    vh = v0 + 0.5 * dt * a
+    assert np.dot(vh[1] - vh[0], x0[1] - x0[0]) > 0  # the half kick made them separate
+    x1 = x0 + dt * vh
+    a1_half = accel(x1, vh)
+    a1_start = accel(x1, v0)
+    assert not np.allclose(a1_half, a1_start)  # the two readings differ here
+    v1 = vh + 0.5 * dt * a1_half
+    run = orc.Run(x0, v0, 1, G, m, dt, 2 * R, 2 * R, 1.0, growth_on=False, law=1, eps=eps,
+                  gamma=gamma, beta=beta)
+    run.advance(1)
+    assert np.allclose(run.pos, x1, rtol=0, atol=1e-15)
+    assert np.allclose(run.vel, v1, rtol=0, atol=1e-12)
