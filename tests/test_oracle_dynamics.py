@@ -207,3 +207,19 @@ def test_growth_off_keeps_diameter(orc):
     run = orc.Run(pos, np.zeros((2, 3)), 1, 1.0, 1e-3, 1e-4, 0.01, 0.02, 0.5, growth_on=False)
     _, d2 = run.advance(10)
     assert np.all(d2 == 0.02)
+
+
+def test_diagnostics_hand_values(orc):
+    """COM, P, L and KE of a hand-placed configuration: a rotating pair plus a drifting third
+    element, values worked out by hand."""
+    m = 0.25
+    pos = np.array([[1.0, 0.0, 0.0], [-1.0, 0.0, 0.0], [0.0, 0.0, 2.0]])
+    vel = np.array([[0.0, 1.0, 0.0], [0.0, -1.0, 0.0], [3.0, 0.0, 0.0]])
+    d = orc.diag(pos, vel, 2, 1.0, m, 0.01, 0.01, with_pe=False)
+    assert np.allclose(d["com"], [0.0, 0.0, 2.0 / 3.0], atol=1e-15)
+    assert np.allclose(d["P"], [3.0 * m, 0.0, 0.0], atol=1e-15)
+    # L = sum m r x v: the pair gives m (0, 0, 1) twice; the third element has r = (0, 0, 2),
+    # v = (3, 0, 0), r x v = (0, 6, 0)
+    assert np.allclose(d["L"], [0.0, 6.0 * m, 2.0 * m], atol=1e-15)
+    assert abs(d["KE"] - 0.5 * m * (1.0 + 1.0 + 9.0)) < 1e-15
+    assert d["PE"] == 0.0
