@@ -29,6 +29,9 @@
  *    (float for the FP32 modes, double for NB_FP64). Star 1 (the accretor, mass 1) owns indices
  *    [0, n1), star 2 (the donor, mass q) owns [n1, n).
  *  - A system's buffers must not be used by another system at the same time.
+ *  - A system belongs to the device that is current when nb_create runs (its buffers must be on
+ *    that device). Every later call naming the system must be made with that device current;
+ *    otherwise the call returns NB_E_INVAL and queues nothing.
  */
 #ifndef NBODY_H
 #define NBODY_H
@@ -120,7 +123,8 @@ typedef struct {
  * invalid parameters. */
 int nb_scratch_bytes(const nb_params *p, size_t *out);
 
-/* Validates p and b, lays out the workspace, initialises the device state (FP64 diameters and
+/* Validates p and b (every buffer must be device or managed memory of the current device; host
+ * memory, pinned or not, is NB_E_INVAL), lays out the workspace, initialises the device state (FP64 diameters and
  * growth flag, derived FP32 force constants), sets every donor element's L1 side from the
  * initial positions and evaluates the initial accelerations a(x0) into ax/ay/az, all ordered on
  * `stream`, which it synchronises before returning. On success *out owns a new handle (free with

@@ -290,16 +290,25 @@ int launch_force_timed(const Launch &L, int mode, hipStream_t st, bool need_comb
         timed = g_timing.on;
     }
     if (timed) {
-        NB_TRY(hipEventCreate(&a));
-        NB_TRY(hipEventCreate(&b));
-        NB_TRY(hipEventRecord(a, st));
+        // events are destroyed on every failure path, so a failed launch leaks nothing
+        if (hipEventCreate(&a) != hipSuccess) return NB_E_HIP;
+        if (hipEventCreate(&b) != hipSuccess || hipEventRecord(a, st) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+            return NB_E_HIP;
+        }
     }
-    NB_TRY(launch_forces(L, mode, g_force_grid.load(), st));
+    const hipError_t e = launch_forces(L, mode, g_force_grid.load(), st);
     if (timed) {
-        NB_TRY(hipEventRecord(b, st));
+        if (e != hipSuccess || hipEventRecord(b, st) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            return NB_E_HIP;
+        }
         std::lock_guard<std::mutex> g(g_timing.mu);
         g_timing.pending.emplace_back(a, b);
     }
+    if (e != hipSuccess) return NB_E_HIP;
     if (need_combine) NB_TRY(launch_combine(L, mode, st));
     return NB_OK;
 }
@@ -333,12 +342,33 @@ Launch single_launch(const nb_system *s)
 
 bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
+// A system's buffers live on the device that was current at nb_create; every later call must be
+// made with that device current, or its kernels would be queued on another GPU.
+bool device_buffer(const void *ptr, int device)
+{
+    // device (or managed) memory of `device`; host memory, pinned or not, is refused, so a
+    // wrong pointer is reported instead of reaching a kernel
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, ptr) != hipSuccess) {
+        (void)hipGetLastError();  // the failed query must not linger as the thread's last error
+        return false;
+    }
+    return (at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged) &&
+           at.device == device;
+}
+
+bool on_own_device(const nb_system *s)
+{
+    int d = -1;
+    return hipGetDevice(&d) == hipSuccess && d == s->device;
+}
+
 int check_system_list(nb_system *const *sys, int32_t n_sys)
 {
     if (!sys || n_sys < 1) return NB_E_INVAL;
     int64_t units = 0, ounits = 0, tiles = 0;
     for (int k = 0; k < n_sys; ++k) {
-        if (!sys[k]) return NB_E_INVAL;
+        if (!sys[k] || !on_own_device(sys[k])) return NB_E_INVAL;
         if (sys[k]->p.mode != sys[0]->p.mode) return NB_E_MISMATCH;
         if (sys[k]->p.law != sys[0]->p.law) return NB_E_MISMATCH;
         for (int j = 0; j < k; ++j) {
@@ -452,6 +482,15 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
     if (cfg.n_units < 0) return NB_E_NOMEM;
     Layout lay = layout_for(p->mode, p->law, cfg);
     if (b->scratch_bytes < lay.total) return NB_E_NOMEM;
+    int device = -1;
+    if (hipGetDevice(&device) != hipSuccess) return NB_E_HIP;
+    if (!device_buffer(b->scratch, device)) return NB_E_INVAL;
+    if (p->n > 0) {
+        const void *arr[10] = {b->x, b->y, b->z, b->vx, b->vy, b->vz, b->ax, b->ay, b->az, b->side};
+        for (const void *a : arr) {
+            if (!device_buffer(a, device)) return NB_E_INVAL;
+        }
+    }
 
     nb_system *s = new (std::nothrow) nb_system();
     if (!s) return NB_E_NOMEM;
@@ -459,10 +498,7 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
     s->b = *b;
     s->cfg = cfg;
     s->lay = lay;
-    if (hipGetDevice(&s->device) != hipSuccess) {
-        delete s;
-        return NB_E_HIP;
-    }
+    s->device = device;
     char *base = static_cast<char *>(b->scratch);
     s->d_state = reinterpret_cast<DevState *>(base + lay.state);
     s->d_desc = reinterpret_cast<SysDesc *>(base + lay.desc);
@@ -644,7 +680,7 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
 
 int nb_forces(nb_system *s, void *stream)
 {
-    if (!s) return NB_E_INVAL;
+    if (!s || !on_own_device(s)) return NB_E_INVAL;
     return launch_force_timed(single_launch(s), s->p.mode, static_cast<hipStream_t>(stream),
                               s->cfg.nsplit > 1 || s->cfg.sym);
 }
@@ -786,7 +822,7 @@ void nb_graph_destroy(nb_graph *g)
 
 int nb_diagnostics(nb_system *s, int32_t with_pe, nb_diag *out, void *stream)
 {
-    if (!s || !out) return NB_E_INVAL;
+    if (!s || !out || !on_own_device(s)) return NB_E_INVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
     NB_TRY(launch_diag(single_launch(s), s->p.mode, with_pe ? 1 : 0, st));
     DiagOut d;
@@ -816,7 +852,7 @@ int nb_diagnostics(nb_system *s, int32_t with_pe, nb_diag *out, void *stream)
 
 int nb_retention(nb_system *s, int32_t *n_past, int32_t *n_bound, void *stream)
 {
-    if (!s || !n_past || !n_bound) return NB_E_INVAL;
+    if (!s || !n_past || !n_bound || !on_own_device(s)) return NB_E_INVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
     NB_TRY(launch_retention(single_launch(s), s->p.mode, st));
     DevState ds;
@@ -829,7 +865,8 @@ int nb_retention(nb_system *s, int32_t *n_past, int32_t *n_bound, void *stream)
 
 int nb_l1_log(nb_system *s, int32_t *out_host, int32_t max_steps, int32_t *n_out, void *stream)
 {
-    if (!s || !n_out || max_steps < 0 || (max_steps > 0 && !out_host)) return NB_E_INVAL;
+    if (!s || !n_out || max_steps < 0 || (max_steps > 0 && !out_host) || !on_own_device(s))
+        return NB_E_INVAL;
     hipStream_t st = static_cast<hipStream_t>(stream);
     std::vector<int32_t> log((size_t)L1_LOG_CAP * 4);
     DevState ds;

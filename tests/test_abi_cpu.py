@@ -114,6 +114,16 @@ def test_create_rejects_small_scratch(nb):
     assert e.value.status == nb.NB_E_NOMEM
 
 
+def test_create_refuses_pointers_it_cannot_verify(nb):
+    # aligned fake addresses and enough scratch: the pointer check (HIP's pointer attributes)
+    # refuses them before any copy or launch; without a GPU the device query fails first
+    p = _params(nb)
+    b = nb.NbBuffers(*([256] * 11), nb.nb_scratch_bytes(p))
+    with pytest.raises(nb.NbError) as e:
+        nb.nb_create(p, b)
+    assert e.value.status in (nb.NB_E_HIP, nb.NB_E_INVAL)
+
+
 def test_step_rejects_bad_arguments(nb):
     lib = nb.load()
     assert lib.nb_step(None, 1, 1, None) == nb.NB_E_INVAL

@@ -110,3 +110,43 @@ def test_coincident_elements(mode, law):
     else:
         ref = oracle.accel(p64, ic.n1, ic.G, ic.m, ic.D1, ic.D2)
     assert force_error(a, ref) <= (1e-5 if mode == "kahan" else 1e-11)
+
+
+def test_create_refuses_host_memory():
+    """Buffers in pinned host memory (device-accessible, so a missed check would not fault) are
+    refused by nb_create with NB_E_INVAL before any copy or launch, the failed pointer query
+    leaves no error behind for the next HIP call, and a valid system builds afterwards."""
+    nb = require_gpu()
+    import torch
+
+    print_case("host buffers refused")
+    ic = synth.make_binary(600, 0.5, seed=12)
+    p = nb.NbParams(n=ic.n, n1=ic.n1, G=ic.G, m=ic.m, dt=1e-4, D1=ic.D1, D2=ic.D2, q=ic.q, a=1.0,
+                    R2_0=0.2, growth_rate=1e-4, growth_on=1, mode=nb.NB_FP32_KAHAN, law=0, pad=0,
+                    eps=0.0, gamma=0.0, beta=1.0)
+    nbytes = nb.nb_scratch_bytes(p)
+    dev = [torch.zeros(ic.n, dtype=torch.float32, device="cuda") for _ in range(9)]
+    host = [torch.zeros(ic.n, dtype=torch.float32, pin_memory=True) for _ in range(9)]
+    side_d = torch.zeros(ic.n, dtype=torch.int8, device="cuda")
+    side_h = torch.zeros(ic.n, dtype=torch.int8, pin_memory=True)
+    scr_d = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    scr_h = torch.empty(nbytes + 256, dtype=torch.uint8, pin_memory=True)
+
+    def bufs(arrays, side, scr):
+        base = scr.data_ptr()
+        names = ("x", "y", "z", "vx", "vy", "vz", "ax", "ay", "az")
+        kw = {k: t.data_ptr() for k, t in zip(names, arrays)}
+        return nb.NbBuffers(side=side.data_ptr(), scratch=base + (-base) % 256,
+                            scratch_bytes=nbytes, **kw)
+
+    for arrays, side, scr in ((host, side_d, scr_d), (dev[:3] + host[3:], side_d, scr_d),
+                              (dev, side_h, scr_d), (dev, side_d, scr_h)):
+        with pytest.raises(nb.NbError) as e:
+            nb.nb_create(p, bufs(arrays, side, scr))
+        assert e.value.status == nb.NB_E_INVAL
+    torch.cuda.synchronize()
+    (dev[0] + 1.0).sum().item()  # no stale HIP error surfaces in torch
+    s = nb.System.from_ic(ic, mode="kahan")
+    a = s.accelerations()
+    s.close()
+    assert np.isfinite(a).all()
