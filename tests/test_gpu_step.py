@@ -163,3 +163,29 @@ def test_nonfinite_state_is_flagged():
     s.close()
     assert d["status"] == nb.NB_E_NONFINITE
     assert d["nonfinite"] > 0
+
+
+@pytest.mark.parametrize("mode", ["kahan", "fp64"])
+def test_growth_enters_the_force_one_step_later(mode):
+    """Growing and non-growing runs from the same start: bitwise equal after one step (the first
+    step's forces use the initial diameter; growth follows the second kick), equal positions
+    and different donor velocities after two (the grown diameter first enters the force at the
+    end of step 2), as in the oracle."""
+    nb = require_gpu()
+    ic = synth.make_binary(2048, 0.5, seed=0)
+    print_case("growth ordering", mode)
+    grow = nb.System.from_ic(ic, mode=mode, growth_on=True)
+    keep = nb.System.from_ic(ic, mode=mode, growth_on=False)
+    grow.step(1)
+    keep.step(1)
+    assert np.array_equal(grow.positions(), keep.positions())
+    assert np.array_equal(grow.velocities(), keep.velocities())
+    assert grow.diagnostics()["D2"] == ic.D2 * (1 + 1e-4)
+    assert keep.diagnostics()["D2"] == ic.D2
+    grow.step(1)
+    keep.step(1)
+    assert np.array_equal(grow.positions(), keep.positions())
+    dv = np.abs(grow.velocities() - keep.velocities()).max(axis=1)
+    grow.close()
+    keep.close()
+    assert (dv[ic.n1:] > 0).any()

@@ -223,3 +223,27 @@ def test_diagnostics_hand_values(orc):
     assert np.allclose(d["L"], [0.0, 6.0 * m, 2.0 * m], atol=1e-15)
     assert abs(d["KE"] - 0.5 * m * (1.0 + 1.0 + 9.0)) < 1e-15
     assert d["PE"] == 0.0
+
+
+def test_growth_applies_after_the_step(orc):
+    """The donor grows after a step's second kick (reading 13). The first step's forces use the
+    initial diameter, so growing and non-growing runs agree exactly after one step, holding D2_0
+    (1 + g) and D2_0. The grown diameter first enters the force at the end of the second step:
+    after it the positions still agree (they moved with the first step's forces) and the donor
+    velocities differ (the donor pair below is in contact, where the force depends on D2)."""
+    pos = np.array([[-0.6, 0.0, 0.0], [0.5, 0.0, 0.0], [0.515, 0.0, 0.0]])
+    vel = np.array([[0.0, 0.1, 0.0], [0.0, 0.0, 0.01], [0.0, 0.0, -0.01]])
+    args = (pos, vel, 1, 1.0, 1e-3, 1e-3, 0.01, 0.02, 0.5)
+    grow, keep = orc.Run(*args, R2_0=0.2), orc.Run(*args, R2_0=0.2, growth_on=False)
+    _, d_grow = grow.advance(1)
+    _, d_keep = keep.advance(1)
+    assert np.array_equal(grow.pos, keep.pos) and np.array_equal(grow.vel, keep.vel)
+    assert d_grow[0] == 0.02 * (1 + 1e-4) and d_keep[0] == 0.02
+    grow.advance(1)
+    keep.advance(1)
+    assert np.array_equal(grow.pos, keep.pos)
+    dv = np.abs(grow.vel - keep.vel).max(axis=1)
+    assert dv[1] > 0 and dv[2] > 0
+    grow.advance(1)
+    keep.advance(1)
+    assert not np.array_equal(grow.pos[1:], keep.pos[1:])
