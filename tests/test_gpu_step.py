@@ -189,3 +189,24 @@ def test_growth_enters_the_force_one_step_later(mode):
     grow.close()
     keep.close()
     assert (dv[ic.n1:] > 0).any()
+
+
+@pytest.mark.parametrize("mode", ["kahan", "plain", "fp64"])
+def test_l1_count_ballistic_hand_case(mode):
+    """G = 0: straight-line motion. Star 1 at the origin, the donor centre held at x = 1 by two
+    elements moving apart, so L1 (q = 0.5) is the plane x = 0.570752; the element leaving
+    x = 0.60 at speed 0.05 with dt = 0.01 first lies past it after step 59. The per-step record
+    has exactly that one forward crossing (the same case pins the oracle's run)."""
+    nb = require_gpu()
+    print_case("L1 ballistic", mode)
+    pos = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.60, 0.0, 0.0], [1.40, 0.0, 0.0]])
+    vel = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 0.0], [-0.05, 0.0, 0.0], [0.05, 0.0, 0.0]])
+    s = nb.System(pos, vel, 1, G=0.0, m=1e-3, dt=0.01, D1=0.01, D2=0.01, q=0.5, growth_on=False,
+                  mode=mode)
+    s.step(80)
+    log = s.l1_log(80)
+    s.close()
+    assert np.array_equal(log[:, 0], np.arange(1, 81))
+    past, fwd, bwd = log[:, 1], log[:, 2], log[:, 3]
+    assert np.all(past[:58] == 0) and np.all(past[58:] == 1)
+    assert fwd[58] == 1 and fwd.sum() == 1 and bwd.sum() == 0

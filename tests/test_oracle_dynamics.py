@@ -247,3 +247,19 @@ def test_growth_applies_after_the_step(orc):
     grow.advance(1)
     keep.advance(1)
     assert not np.array_equal(grow.pos[1:], keep.pos[1:])
+
+
+def test_l1_count_inside_a_run_ballistic(orc):
+    """The count of a run uses each step's final positions. With G = 0 the elements move on
+    straight lines. Here the donor centre stays at x = 1 (two elements move apart symmetrically)
+    and star 1 sits at the origin, so L1 (q = 0.5) is the plane x = 0.570752. The element from
+    x = 0.60 at speed 0.05 (dt = 0.01) is at 0.60 - 0.0005 k after step k, first below the plane
+    at k = 59: one forward crossing there, one element past L1 from then on."""
+    pos = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.60, 0.0, 0.0], [1.40, 0.0, 0.0]])
+    vel = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 0.0], [-0.05, 0.0, 0.0], [0.05, 0.0, 0.0]])
+    run = orc.Run(pos, vel, 1, 0.0, 1e-3, 0.01, 0.01, 0.01, 0.5, growth_on=False)
+    counts, _ = run.advance(80)
+    past, fwd, bwd = counts[:, 0], counts[:, 1], counts[:, 2]
+    assert np.all(past[:58] == 0) and np.all(past[58:] == 1)
+    assert fwd[58] == 1 and fwd.sum() == 1 and bwd.sum() == 0
+    assert run.pos[2, 0] == pytest.approx(0.60 - 0.05 * 0.8, abs=1e-12)
