@@ -210,3 +210,36 @@ def test_l1_count_ballistic_hand_case(mode):
     past, fwd, bwd = log[:, 1], log[:, 2], log[:, 3]
     assert np.all(past[:58] == 0) and np.all(past[58:] == 1)
     assert fwd[58] == 1 and fwd.sum() == 1 and bwd.sum() == 0
+
+
+@pytest.mark.parametrize("mode,tol", [("fp64", 1e-12), ("kahan", 5e-6), ("plain", 5e-6)])
+def test_contact_oscillation_matches_the_leapfrog_closed_form(mode, tol):
+    """Two elements of one star in contact, moving apart at relative speed v0. Inside D the
+    contact law is affine, f = (11 G m^2 / D^3) (r - 10 D / 11), so the separation u = r - r_eq
+    obeys u'' = -w^2 u (w^2 = 22 G m / D^3), and the leap-frog map of a linear force is exactly
+    u_k = u_0 cos(k theta) + (v_0 dt / sin theta) sin(k theta), cos theta = 1 - (w dt)^2 / 2
+    (the oracle meets it to 1.6e-14). Bars, each the worst case of rounding errors adding up in
+    one direction: FP64, a few roundings of 0.05-sized positions (1.1e-17 each) per step over
+    2000 steps, 1e-13, with margin; FP32, half an ulp of 0.05 (1.9e-9) per step over 2000 steps
+    plus the FP32 rounding of 11/D^3 and 10/D^2, about 4e-6 (measured: 1.6e-14 and 1.0e-7;
+    amplitude 2.9e-3)."""
+    nb = require_gpu()
+    print_case("contact oscillator", mode)
+    D, m, dt, u0, v0 = 0.1, 1e-3, 1e-3, 0.002, 0.01
+    r_eq = 10.0 * D / 11.0
+    r0 = r_eq + u0
+    pos = np.array([[-0.5 * r0, 0.0, 0.0], [0.5 * r0, 0.0, 0.0]])
+    vel = np.array([[-0.5 * v0, 0.0, 0.0], [0.5 * v0, 0.0, 0.0]])
+    theta = math.acos(1.0 - 22.0 * m / D ** 3 * dt * dt / 2.0)
+    s = nb.System(pos, vel, 2, G=1.0, m=m, dt=dt, D1=D, D2=D, q=0.5, growth_on=False, mode=mode)
+    done, worst = 0, 0.0
+    for k in (1, 250, 1000, 2000):
+        s.step(k - done)
+        done = k
+        p = s.positions().astype(np.float64)
+        u = (p[1, 0] - p[0, 0]) - r_eq
+        exact = u0 * math.cos(k * theta) + v0 * dt / math.sin(theta) * math.sin(k * theta)
+        worst = max(worst, abs(u - exact))
+    s.close()
+    print("worst |u - closed form| = %.3e" % worst)
+    assert worst < tol
