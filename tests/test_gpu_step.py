@@ -212,10 +212,12 @@ def test_l1_count_ballistic_hand_case(mode):
     assert fwd[58] == 1 and fwd.sum() == 1 and bwd.sum() == 0
 
 
+@pytest.mark.parametrize("n1,D1,D2", [(2, 0.1, 0.1), (1, 0.08, 0.12)])
 @pytest.mark.parametrize("mode,tol", [("fp64", 1e-12), ("kahan", 5e-6), ("plain", 5e-6)])
-def test_contact_oscillation_matches_the_leapfrog_closed_form(mode, tol):
-    """Two elements of one star in contact, moving apart at relative speed v0. Inside D the
-    contact law is affine, f = (11 G m^2 / D^3) (r - 10 D / 11), so the separation u = r - r_eq
+def test_contact_oscillation_matches_the_leapfrog_closed_form(mode, tol, n1, D1, D2):
+    """Two elements in contact, both in star 1 (D = D1) or one in each star (D = (D1 + D2) / 2),
+    moving apart at relative speed v0. Inside D the contact law is affine,
+    f = (11 G m^2 / D^3) (r - 10 D / 11), so the separation u = r - r_eq
     obeys u'' = -w^2 u (w^2 = 22 G m / D^3), and the leap-frog map of a linear force is exactly
     u_k = u_0 cos(k theta) + (v_0 dt / sin theta) sin(k theta), cos theta = 1 - (w dt)^2 / 2
     (the oracle meets it to 1.6e-14). Bars, each the worst case of rounding errors adding up in
@@ -231,7 +233,8 @@ def test_contact_oscillation_matches_the_leapfrog_closed_form(mode, tol):
     pos = np.array([[-0.5 * r0, 0.0, 0.0], [0.5 * r0, 0.0, 0.0]])
     vel = np.array([[-0.5 * v0, 0.0, 0.0], [0.5 * v0, 0.0, 0.0]])
     theta = math.acos(1.0 - 22.0 * m / D ** 3 * dt * dt / 2.0)
-    s = nb.System(pos, vel, 2, G=1.0, m=m, dt=dt, D1=D, D2=D, q=0.5, growth_on=False, mode=mode)
+    s = nb.System(pos, vel, n1, G=1.0, m=m, dt=dt, D1=D1, D2=D2, q=0.5, growth_on=False,
+                  mode=mode)
     done, worst = 0, 0.0
     for k in (1, 250, 1000, 2000):
         s.step(k - done)

@@ -284,14 +284,16 @@ def _contact_oscillator(D=0.1, m=1e-3, dt=1e-3, u0=0.002, v0=0.01):
     return pos, vel, u_exact, 10.0 * D / 11.0, amp
 
 
-def test_contact_oscillation_matches_the_leapfrog_closed_form(orc):
-    """Bar: FP64 rounding of positions of size 0.05, accumulated over 2000 steps (measured
-    7e-15 at step 1000). A wrong stiffness, sign or integrator variant (drift-kick-drift, Euler)
-    misses it by orders of magnitude."""
+@pytest.mark.parametrize("n1,D1,D2", [(2, 0.1, 0.1), (1, 0.08, 0.12)])
+def test_contact_oscillation_matches_the_leapfrog_closed_form(orc, n1, D1, D2):
+    """Both elements in star 1 (D = D1), or one in each star (D = (D1 + D2) / 2 = 0.1). Bar:
+    FP64 rounding of positions of size 0.05, accumulated over 2000 steps (measured 1.6e-14). A
+    wrong stiffness, sign, pair diameter or integrator variant (drift-kick-drift, Euler) misses
+    it by orders of magnitude."""
     D, m, dt = 0.1, 1e-3, 1e-3
     pos, vel, u_exact, r_eq, amp = _contact_oscillator(D, m, dt)
     assert r_eq + amp < D and r_eq - amp > 0  # the separation stays where the law is affine
-    run = orc.Run(pos, vel, 2, 1.0, m, dt, D, D, 0.5, growth_on=False)
+    run = orc.Run(pos, vel, n1, 1.0, m, dt, D1, D2, 0.5, growth_on=False)
     done = 0
     for k in (1, 250, 1000, 2000):
         run.advance(k - done)
