@@ -226,7 +226,8 @@ def test_diagnostics_hand_values(orc):
 
 
 def test_growth_applies_after_the_step(orc):
-    """The donor grows after a step's second kick (reading 13). The first step's forces use the
+    """The donor grows after a step's second kick (the paper does not fix the order within a
+    step; this is the order taken on both sides). The first step's forces use the
     initial diameter, so growing and non-growing runs agree exactly after one step, holding D2_0
     (1 + g) and D2_0. The grown diameter first enters the force at the end of the second step:
     after it the positions still agree (they moved with the first step's forces) and the donor
