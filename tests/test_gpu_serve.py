@@ -65,13 +65,18 @@ def _small_trace(count=10, steps=30, rate=400.0, seed=5):
                             seed=seed)
 
 
-@pytest.mark.parametrize("policy", ["srpt", "all"])
-def test_server_results_equal_sequential_results(policy):
+@pytest.mark.parametrize("policy,use_graphs,depth", [("srpt", True, 2), ("all", True, 2),
+                                                     ("srpt", False, 2), ("srpt", True, 1)])
+def test_server_results_equal_sequential_results(policy, use_graphs, depth):
+    """Every policy, with captured graphs or plain multi-system steps, one or two rounds queued:
+    each request's final state equals its one-at-a-time run bit for bit."""
     require_gpu()
     from paper_2303_12166_amd import serve
 
+    print_case("serve", policy, "graphs" if use_graphs else "nb_step", "depth", depth)
     trace = _small_trace()
-    server = serve.BatchServer(budget_bytes=8 << 30, round_steps=7, policy=policy, fill=2e8)
+    server = serve.BatchServer(budget_bytes=8 << 30, round_steps=7, policy=policy, fill=2e8,
+                               use_graphs=use_graphs, depth=depth)
     batched = server.run(trace)
     seq = serve.run_sequential(trace, chunk=11)
     assert all(r.status == "done" for r in batched)
@@ -82,7 +87,7 @@ def test_server_results_equal_sequential_results(policy):
     s = serve.summarize(batched)
     assert s["completed"] == len(trace)
     assert s["latency_p99_s"] >= s["latency_p50_s"] > 0
-    assert server.graphs_built >= 1
+    assert (server.graphs_built >= 1) == use_graphs
 
 
 def test_server_admission_under_small_budget():
