@@ -246,3 +246,26 @@ def test_contact_oscillation_matches_the_leapfrog_closed_form(mode, tol, n1, D1,
     s.close()
     print("worst |u - closed form| = %.3e" % worst)
     assert worst < tol
+
+
+def test_l1_log_keeps_the_last_4096_steps():
+    """The per-step L1 record is a ring of NB_L1_LOG_CAP = 4096 rows: after 4100 steps the
+    oldest rows are gone, the rows come back oldest first with contiguous step numbers, a shorter
+    request returns the most recent rows, and the newest row equals the last step's counts that
+    nb_diagnostics reports."""
+    nb = require_gpu()
+    print_case("L1 log ring")
+    ic = synth.make_binary(512, 0.5, seed=4)
+    s = nb.System.from_ic(ic, mode="kahan", dt=1e-3)
+    s.step(4100)
+    full = s.l1_log(5000)
+    last = s.l1_log(10)
+    d = s.diagnostics()
+    s.close()
+    assert full.shape == (nb.NB_L1_LOG_CAP, 4)
+    assert np.array_equal(full[:, 0], np.arange(4100 - 4096 + 1, 4101))
+    assert np.array_equal(last, full[-10:])
+    assert d["step"] == 4100
+    assert tuple(full[-1, 1:]) == (d["n_past_L1"], d["cross_fwd"], d["cross_bwd"])
+    # every row is a consistent count: the past count changes by forward minus backward
+    assert np.array_equal(np.diff(full[:, 1]), full[1:, 2] - full[1:, 3])
