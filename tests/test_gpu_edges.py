@@ -150,3 +150,31 @@ def test_create_refuses_host_memory():
     a = s.accelerations()
     s.close()
     assert np.isfinite(a).all()
+
+
+def test_force_timing_counts_exactly_the_timed_launches():
+    """nb_timing_*: while enabled, each force launch of nb_forces and nb_step is timed once;
+    nothing is counted while disabled, graph replays are not counted, and a reset clears the
+    totals."""
+    nb = require_gpu()
+    print_case("force timing")
+    ic = synth.make_binary(4096, 0.5, seed=2)
+    s = nb.System.from_ic(ic, mode="kahan")
+    nb.nb_timing_reset()
+    nb.nb_timing_enable(True)
+    s.forces()
+    s.forces()
+    s.step(3)
+    g = nb.nb_graph_create([s.handle], 2, s.stream)
+    nb.nb_graph_launch(g, s.stream)
+    nb.nb_timing_enable(False)
+    s.forces()
+    s.step(2)
+    s.synchronize()
+    ms, n = nb.nb_timing_read()
+    nb.nb_graph_destroy(g)
+    s.close()
+    assert n == 5
+    assert 0.0 < ms < 1000.0
+    nb.nb_timing_reset()
+    assert nb.nb_timing_read() == (0.0, 0)
