@@ -269,3 +269,19 @@ def test_l1_log_keeps_the_last_4096_steps():
     assert tuple(full[-1, 1:]) == (d["n_past_L1"], d["cross_fwd"], d["cross_bwd"])
     # every row is a consistent count: the past count changes by forward minus backward
     assert np.array_equal(np.diff(full[:, 1]), full[1:, 2] - full[1:, 3])
+
+
+def test_no_growth_when_the_donor_starts_beyond_its_lobe():
+    """q = 0.1: r_L = 0.1992 < R2_0 = 0.2, so the first step stops growth and D2 stays D2_0, as
+    in the oracle."""
+    nb = require_gpu()
+    print_case("no growth at q = 0.1")
+    ic = synth.make_binary(2048, 0.1, seed=0)
+    s = nb.System.from_ic(ic, mode="kahan")
+    s.step(1)
+    d1 = s.diagnostics()
+    s.step(4)
+    d5 = s.diagnostics()
+    s.close()
+    assert d1["growth_stopped"] and d5["growth_stopped"]
+    assert d1["D2"] == ic.D2 and d5["D2"] == ic.D2

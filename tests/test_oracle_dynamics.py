@@ -302,3 +302,13 @@ def test_contact_oscillation_matches_the_leapfrog_closed_form(orc, n1, D1, D2):
         p = run.pos
         assert abs((p[1, 0] - p[0, 0]) - r_eq - u_exact(k)) < 2e-13
         assert abs(p[0, 0] + p[1, 0]) < 1e-15  # the centre of mass stays at the origin
+
+
+def test_no_growth_when_the_donor_starts_beyond_its_lobe(orc):
+    """At q = 0.1 the lobe radius r_L = 0.1992 is below the initial donor radius 0.2, so the first
+    growth check stops growth for good and the diameter never changes."""
+    assert orc.roche_lobe(0.1) < 0.2 < orc.roche_lobe(0.102)
+    pos = np.array([[-0.5, 0, 0], [0.5, 0, 0]])
+    run = orc.Run(pos, np.zeros((2, 3)), 1, 1.0, 1e-3, 1e-4, 0.01, 0.02, 0.1, R2_0=0.2)
+    _, d2 = run.advance(5)
+    assert np.all(d2 == 0.02) and run.growth_stopped
