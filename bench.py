@@ -44,7 +44,9 @@ KERNEL_NAMES = {"kahan": "k_force_sym", "plain": "k_force_f32<1,false>",
                 "fp64": "k_force_f64<0>"}
 PAPER_KERNEL_NAMES = {"kahan": "k_force_sym_paper", "fp64": "k_force_f64<1>"}
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "force_counters.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2303_12166_amd", "csrc", "nb_kernels.hip")
+# the sources that decide the kernels' machine code: the kernels and their compile-time knobs
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2303_12166_amd", "csrc", f)
+               for f in ("nb_internal.h", "nb_kernels.hip")]
 
 
 def log(*a):
@@ -52,8 +54,11 @@ def log(*a):
 
 
 def kernel_source_sha() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def counter_record(workload: str, mode: str, nsplit: int):

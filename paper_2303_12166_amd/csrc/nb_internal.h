@@ -33,7 +33,8 @@ namespace nbk {
 #define NB_SYM_WAVES_PER_EU 6
 #endif
 #ifndef NB_SYM_PAPER_WAVES_PER_EU
-#define NB_SYM_PAPER_WAVES_PER_EU 5  // eqs. (4)-(6) variant: more live values per pair
+#define NB_SYM_PAPER_WAVES_PER_EU 6  // eqs. (4)-(6) variant: a few per-tile values spill, none
+                                     // inside the pair loop; faster than 5 waves without spills
 #endif
 #if NB_WAVES_PER_EU > 0
 #define NB_FORCE_ATTR __attribute__((amdgpu_waves_per_eu(NB_WAVES_PER_EU)))

@@ -540,6 +540,24 @@ __device__ __forceinline__ void sym_tile(const float4 *__restrict__ sj,
     }
 }
 
+// A value that is the same in every lane, moved to a scalar register.
+__device__ __forceinline__ float wave_uniform(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ LawF law_uniform(LawF K)
+{
+    K.c1 = wave_uniform(K.c1);
+    K.nc2 = wave_uniform(K.nc2);
+    K.D = wave_uniform(K.D);
+    K.twoD = wave_uniform(K.twoD);
+    K.eps = wave_uniform(K.eps);
+    K.gc = wave_uniform(K.gc);
+    K.gcb = wave_uniform(K.gcb);
+    return K;
+}
+
 __device__ __forceinline__ LawF law_f(const DevState *st, int cls)
 {
     LawF K;
@@ -602,8 +620,21 @@ __device__ void force_unit_sym(const SysDesc &S, int grp, int c, float4 *sj, flo
     hi[1] = wave_max(real ? Ist.y[0] : -INFINITY);
     hi[2] = wave_max(real ? Ist.z[0] : -INFINITY);
     const int istar = I * TJ >= S.p1 ? 1 : 0;
-    const LawF Ka = law_f(st, istar), Kb = law_f(st, istar + 1);
-    const float far2a = st->far2f[istar], far2b = st->far2f[istar + 1];
+    LawF Ka = law_f(st, istar), Kb = law_f(st, istar + 1);
+    float far2a = st->far2f[istar], far2b = st->far2f[istar + 1];
+    if constexpr (LAW != 0) {
+        // the box and the constants are the same in every lane; held in scalar registers they
+        // leave the eqs. (4)-(6) kernel enough vector registers for six waves per SIMD without
+        // spilling
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = wave_uniform(lo[d]);
+            hi[d] = wave_uniform(hi[d]);
+        }
+        Ka = law_uniform(Ka);
+        Kb = law_uniform(Kb);
+        far2a = wave_uniform(far2a);
+        far2b = wave_uniform(far2b);
+    }
 
     float sumx = 0.f, sumy = 0.f, sumz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
     const int t0 = g0 + c * S.ch;
