@@ -194,8 +194,8 @@ int nb_timing_read(double *total_ms, int64_t *launches);
 int nb_timing_reset(void);
 
 /* Work split chosen for a system of n elements (n1 in star 1) in a mode: i elements per lane
- * (ki), j chunks per i-block (nsplit; for the symmetric FP32 Kahan kernel, the chunk count of
- * the longest tile row), i-block size and chunk length (in sorted slots). The
+ * (ki), j chunks per i-block (nsplit; for the symmetric kernels of the FP32 Kahan and FP64 modes,
+ * the chunk count of the longest tile row), i-block size and chunk length (in sorted slots). The
  * force kernels work on a copy of the positions sorted per star (Morton order of the initial
  * positions, each star padded to a multiple of 256 slots); results are returned in element
  * order. Depends only on (n, n1, mode) and the overrides below. Any output pointer may be NULL. */

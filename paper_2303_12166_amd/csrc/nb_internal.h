@@ -57,6 +57,12 @@ constexpr int TJ = 256;          // j elements staged in LDS per tile (one per t
 constexpr int KI32 = NB_KI32;    // i elements per lane, FP32 force kernel
 constexpr int KI64 = 1;          // i elements per lane, FP64 force kernel
 constexpr int SYM_ROWS = NB_SYM_ROWS;  // tile rows per block of the symmetric kernel
+// The FP64 mode uses the symmetric scheme too (k_force_sym64), with one tile row per block; a
+// build with two rows per block keeps the one-sided FP64 kernel.
+#ifndef NB_FP64_SYM
+#define NB_FP64_SYM 1
+#endif
+constexpr bool FP64_SYM = NB_FP64_SYM != 0 && SYM_ROWS == 1;
 constexpr int RED_STRIDE = 32;   // doubles per O(N)-unit partial record
 constexpr int RED_STEP = 0;      // record slots [0, 16): per-step sums (COMs, flags, L1 counts)
 constexpr int RED_DIAG = 16;     // record slots [16, 32): diagnostics sums

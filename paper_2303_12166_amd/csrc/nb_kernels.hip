@@ -2,12 +2,13 @@
 //
 // The O(N^2) all-pairs force evaluation (Methodology: every element moves only under the sum of
 // all pairwise element-element interactions) is the hot path. It runs on the FP32 vector ALUs:
-// the pair sum is not a dense contraction, so there is no MFMA here. Three kernels evaluate it:
+// the pair sum is not a dense contraction, so there is no MFMA here. The kernels that evaluate it:
 //   - k_force_sym (FP32, Kahan mode, the default): each unordered pair once, i in registers and
 //     the j sums rotating across the wave (see the section below), for both element laws;
 //   - k_force_f32 (FP32, plain mode): one-sided, each lane keeps KI i elements and the block
 //     streams 256-element SoA j tiles through LDS (broadcast ds_read_b128), one FP32 running sum;
-//   - k_force_f64 (FP64 reference mode): one-sided, both element laws.
+//   - k_force_sym64 (FP64 reference mode): the symmetric scheme in FP64, both element laws;
+//     k_force_f64, one-sided, takes its place in builds with two tile rows per block.
 // All of them work on a Morton-sorted, star-by-star padded copy of the positions; the FP32 ones
 // skip the contact test on tiles whose bounding boxes are at least D apart. Per pair of the
 // contact law:
@@ -970,6 +971,200 @@ __global__ __launch_bounds__(BT) void k_force_f64(Launch L)
     }
 }
 
+// ------------------------------------------------------------------ FP64 symmetric force kernel
+//
+// The FP64 reference mode with the work split of k_force_sym (one tile row per block): each
+// unordered pair once, i in registers, the j sums rotating across the wave (a double moves as its
+// two 32-bit halves, one DPP move each), the diagonal tile one-sided, reactions stored per (tile
+// row, later tile) and added by k_combine_sym64 after the element's own chunk partials, rows in
+// order. Every sum is plain FP64 in a fixed order. There is no far-tile path: the tile boxes are
+// FP32, and every pair takes the full law.
+
+__device__ __forceinline__ double wave_ror1_d(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), DPP_WAVE_ROR1, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), DPP_WAVE_ROR1, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+
+struct I64 {
+    double x, y, z, vx, vy, vz;
+};
+
+template <int LAW>
+__device__ __forceinline__ double pair_s64_at(const double (*sj)[TJ], const double (*sv)[TJ], int j,
+                                              const I64 &I, double D, double c1, double c2,
+                                              const DevState *st, double &dx, double &dy,
+                                              double &dz)
+{
+    dx = sj[0][j] - I.x;
+    dy = sj[1][j] - I.y;
+    dz = sj[2][j] - I.z;
+    const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+    const double w = r2 > 0.0 ? rsqrt_f64(r2) : 0.0;
+    if constexpr (LAW == 0) {
+        return pair_s64<0>(r2, w, dx, dy, dz, 0.0, 0.0, 0.0, D, c1, c2, st);
+    } else {
+        return pair_s64<LAW>(r2, w, dx, dy, dz, sv[0][j] - I.vx, sv[1][j] - I.vy, sv[2][j] - I.vz,
+                             D, c1, c2, st);
+    }
+}
+
+template <int LAW>
+__device__ void force_unit_sym64(const SysDesc &S, int I, int c, double (*sj)[TJ],
+                                 double (*sv)[TJ], double (*rw)[3][TJ])
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double *__restrict__ XS = static_cast<const double *>(S.xs);
+    const double *__restrict__ YS = static_cast<const double *>(S.ys);
+    const double *__restrict__ ZS = static_cast<const double *>(S.zs);
+    const double *__restrict__ VXS = static_cast<const double *>(S.vxs);
+    const double *__restrict__ VYS = static_cast<const double *>(S.vys);
+    const double *__restrict__ VZS = static_cast<const double *>(S.vzs);
+    const DevState *st = S.st;
+    const int T = S.ntiles;
+    const int slot = I * TJ + tid;
+    I64 Ist{XS[slot], YS[slot], ZS[slot], 0.0, 0.0, 0.0};
+    if constexpr (LAW != 0) {
+        Ist.vx = VXS[slot];
+        Ist.vy = VYS[slot];
+        Ist.vz = VZS[slot];
+    }
+    const int istar = I * TJ >= S.p1 ? 1 : 0;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    const int t0 = I + c * S.ch;
+    const int t1 = min(T, t0 + S.ch);
+    double *R = reinterpret_cast<double *>(S.react);
+    const size_t roff = react_group_offset(I, T);
+    const size_t rlen = (size_t)(T - I - 1) * TJ;
+    for (int t = t0; t < t1; ++t) {
+        sj[0][tid] = XS[t * TJ + tid];
+        sj[1][tid] = YS[t * TJ + tid];
+        sj[2][tid] = ZS[t * TJ + tid];
+        if constexpr (LAW != 0) {
+            sv[0][tid] = VXS[t * TJ + tid];
+            sv[1][tid] = VYS[t * TJ + tid];
+            sv[2][tid] = VZS[t * TJ + tid];
+        }
+        __syncthreads();
+        const int cls = pair_class(istar, t * TJ >= S.p1 ? 1 : 0);
+        const double c1 = st->c1d[cls], c2 = st->c2d[cls];
+        const double D = cls == 0 ? st->D1 : (cls == 2 ? st->D2 : 0.5 * (st->D1 + st->D2));
+        if (t == I) {
+            // the self pair (d = 0) gives s = 0 under both laws
+            for (int jj = 0; jj < TJ; ++jj) {
+                double dx, dy, dz;
+                const double s = pair_s64_at<LAW>(sj, sv, jj, Ist, D, c1, c2, st, dx, dy, dz);
+                ax = fma(s, dx, ax);
+                ay = fma(s, dy, ay);
+                az = fma(s, dz, az);
+            }
+        } else {
+            double ajx[4] = {0.0, 0.0, 0.0, 0.0}, ajy[4] = {0.0, 0.0, 0.0, 0.0};
+            double ajz[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int step = 0; step < 64; ++step) {
+                const int e = (lane - step) & 63;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    double dx, dy, dz;
+                    const double s = pair_s64_at<LAW>(sj, sv, g * 64 + e, Ist, D, c1, c2, st, dx,
+                                                      dy, dz);
+                    const double px = s * dx, py = s * dy, pz = s * dz;
+                    ax += px;
+                    ay += py;
+                    az += pz;
+                    ajx[g] = wave_ror1_d(ajx[g]) - px;
+                    ajy[g] = wave_ror1_d(ajy[g]) - py;
+                    ajz[g] = wave_ror1_d(ajz[g]) - pz;
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                // one more rotation brings element l's sum back to lane l
+                rw[wave][0][g * 64 + lane] = wave_ror1_d(ajx[g]);
+                rw[wave][1][g * 64 + lane] = wave_ror1_d(ajy[g]);
+                rw[wave][2][g * 64 + lane] = wave_ror1_d(ajz[g]);
+            }
+            __syncthreads();
+            const size_t at = roff + (size_t)(t - I - 1) * TJ + tid;
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                R[at + d * rlen] = ((rw[0][d][tid] + rw[1][d][tid]) + rw[2][d][tid]) + rw[3][d][tid];
+        }
+        __syncthreads();  // sj, sv and rw are rewritten by the next tile
+    }
+    if (S.perm[slot] >= 0) {
+        double *P = static_cast<double *>(S.part);
+        const size_t na = S.nalloc;
+        const size_t b = (size_t)c * 3 * na + slot;
+        P[b] = ax;
+        P[b + na] = ay;
+        P[b + 2 * na] = az;
+    }
+}
+
+template <int LAW>
+__global__ __launch_bounds__(BT) void k_force_sym64(Launch L)
+{
+    __shared__ double sj[3][TJ];
+    __shared__ double sv[LAW == 0 ? 1 : 3][TJ];
+    __shared__ double rw[4][3][TJ];
+    for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
+        const SysDesc &S = L.sys[find_sys(L, u, false)];
+        const int2 ic = reinterpret_cast<const int2 *>(S.units)[u - S.unit_begin];
+        force_unit_sym64<LAW>(S, ic.x, ic.y, sj, sv, rw);
+    }
+}
+
+// a = G m (sum of the element's own chunk partials, then the reactions of every earlier tile row
+// in row order), plain FP64, scattered to the element's own index.
+__global__ __launch_bounds__(BT) void k_combine_sym64(Launch L)
+{
+    const int e = threadIdx.x;
+    for (int u = blockIdx.x; u < L.total_tunits; u += gridDim.x) {
+        const SysDesc &S = L.sys[find_tile_sys(L, u)];
+        const int J = u - S.tunit_begin;
+        const int T = S.ntiles;
+        const int slot = J * TJ + e;
+        const int idx = S.perm[slot];
+        if (idx < 0) continue;
+        const double *P = static_cast<const double *>(S.part);
+        const double *R = reinterpret_cast<const double *>(S.react);
+        const size_t na = S.nalloc;
+        const int cj = (T - J + S.ch - 1) / S.ch;  // the chunk count of the element's own row
+        double out[3];
+        for (int d = 0; d < 3; ++d) {
+            double sum = 0.0;
+            for (int c = 0; c < cj; ++c) sum += P[(size_t)c * 3 * na + d * na + slot];
+            // rows are read eight at a time (independent loads in flight), then added in row
+            // order; the arithmetic is the same as one row at a time
+            size_t off = 0, len = (size_t)(T - 1) * TJ;
+            int g = 0;
+            for (; g + 8 <= J; g += 8) {
+                double v[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    v[q] = R[off + d * len + slot - (size_t)TJ * (g + q + 1)];
+                    off += 3 * len;
+                    len -= TJ;
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) sum += v[q];
+            }
+            for (; g < J; ++g) {
+                sum += R[off + d * len + slot - (size_t)TJ * (g + 1)];
+                off += 3 * len;
+                len -= TJ;
+            }
+            out[d] = sum;
+        }
+        const double gm = S.st->gm_d;
+        static_cast<double *>(S.ax)[idx] = gm * out[0];
+        static_cast<double *>(S.ay)[idx] = gm * out[1];
+        static_cast<double *>(S.az)[idx] = gm * out[2];
+    }
+}
+
 // ------------------------------------------------------------------ j-split combine
 
 // Sums the chunk partials of each sorted slot in chunk order and scatters a = G m sum to the
@@ -1500,6 +1695,12 @@ hipError_t launch_forces(const Launch &L, int mode, int max_blocks, hipStream_t 
         } else {
             hipLaunchKernelGGL(k_force_sym_paper, g, dim3(BT * SYM_ROWS), 0, s, L);
         }
+    } else if (FP64_SYM) {
+        if (L.law == 0) {
+            hipLaunchKernelGGL(k_force_sym64<0>, g, b, 0, s, L);
+        } else {
+            hipLaunchKernelGGL(k_force_sym64<1>, g, b, 0, s, L);
+        }
     } else {
         if (L.law == 0) {
             hipLaunchKernelGGL(k_force_f64<0>, g, b, 0, s, L);
@@ -1518,6 +1719,8 @@ hipError_t launch_combine(const Launch &L, int mode, hipStream_t s)
         hipLaunchKernelGGL((k_combine<float, false>), g, b, 0, s, L);
     } else if (mode == 1) {
         hipLaunchKernelGGL(k_combine_sym<NB_COMBINE_SEGS>, g, dim3(BT * NB_COMBINE_SEGS), 0, s, L);
+    } else if (FP64_SYM) {
+        hipLaunchKernelGGL(k_combine_sym64, g, b, 0, s, L);
     } else {
         hipLaunchKernelGGL((k_combine<double, false>), g, b, 0, s, L);
     }

@@ -47,8 +47,8 @@ double l1_from_accretor(double q)
 struct TileCfg {
     int ki, nsplit, iblock, jchunk, n_iblocks, n_units, n_ounits;
     int npad, p1, nalloc, ntiles;
-    int sym, ch;            // symmetric kernel (Kahan mode) and its tiles per chunk
-    size_t react_floats;    // reaction partials of the symmetric kernel
+    int sym, ch;            // symmetric kernel (Kahan and FP64 modes) and its tiles per chunk
+    size_t react_floats;    // reaction partials of the symmetric kernel (elements of the mode's type)
 };
 
 struct Override {
@@ -84,7 +84,7 @@ TileCfg tile_config(int64_t n, int64_t n1, int mode)
             if (n >= o.lo && n <= o.hi) ns = o.nsplit;
         }
     }
-    if (mode == NB_FP32_KAHAN && c.ntiles > 0) {
+    if ((mode == NB_FP32_KAHAN || (mode == NB_FP64 && FP64_SYM)) && c.ntiles > 0) {
         // symmetric kernel: group g holds tile rows SYM_ROWS g .. SYM_ROWS g + SYM_ROWS - 1 and
         // covers tiles SYM_ROWS g .. T-1 in chunks of ch tiles; its reactions are stored for the
         // tiles after its first row. nsplit is the chunk count of the longest group.
@@ -143,7 +143,7 @@ Layout layout_for(int mode, int law, const TileCfg &c)
     L.perm = take((size_t)c.nalloc * sizeof(int32_t));
     L.tbox = take((size_t)std::max(c.ntiles, 1) * 8 * sizeof(float));
     L.units = take(c.sym ? (size_t)c.n_units * 2 * sizeof(int32_t) : 0);
-    L.react = take(c.sym ? c.react_floats * sizeof(float) : 0);
+    L.react = take(c.sym ? c.react_floats * elem : 0);
     L.part = off;
     if (c.nsplit > 1 || c.sym) take((size_t)c.nsplit * 3 * (size_t)c.nalloc * elem);
     L.total = off;
