@@ -41,8 +41,8 @@ WORKLOADS = {
 }
 
 KERNEL_NAMES = {"kahan": "k_force_sym", "plain": "k_force_f32<1,false>",
-                "fp64": "k_force_f64<0>"}
-PAPER_KERNEL_NAMES = {"kahan": "k_force_sym_paper", "fp64": "k_force_f64<1>"}
+                "fp64": "k_force_sym64<0>"}
+PAPER_KERNEL_NAMES = {"kahan": "k_force_sym_paper", "fp64": "k_force_sym64<1>"}
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "force_counters.json")
 # the sources that decide the kernels' machine code: the kernels and their compile-time knobs
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2303_12166_amd", "csrc", f)
