@@ -152,17 +152,21 @@ def test_retention_rejects_null_arguments(nb):
 
 
 def test_scratch_bytes_grow_by_sorted_velocities_under_the_paper_law(nb):
-    """NB_LAW_PAPER adds three sorted velocity arrays (nalloc slots each, 256-byte aligned)."""
-    base = _params(nb)
-    paper = _params(nb, law=nb.NB_LAW_PAPER, eps=0.001, gamma=1.0, beta=0.5)
+    """NB_LAW_PAPER adds three sorted velocity arrays (nalloc slots each, 256-byte aligned). The
+    system is large enough that neither law splits its work units by j group (small systems
+    under the contact law hold four times the chunk partials)."""
+    big = dict(n=200000, n1=150000)
+    base = _params(nb, **big)
+    paper = _params(nb, law=nb.NB_LAW_PAPER, eps=0.001, gamma=1.0, beta=0.5, **big)
     extra = nb.nb_scratch_bytes(paper) - nb.nb_scratch_bytes(base)
     # each star padded to whole 256-slot tiles (a multiple of the i-block, so nalloc = slots)
     slots = -(-(base.n1) // 256) * 256 + -(-(base.n - base.n1) // 256) * 256
     per = -(-slots * 4 // 256) * 256
     assert extra == 3 * per
     # FP64: eight bytes per slot
-    b64 = _params(nb, mode=nb.NB_FP64)
-    p64 = _params(nb, mode=nb.NB_FP64, law=nb.NB_LAW_PAPER, eps=0.001, gamma=1.0, beta=0.5)
+    b64 = _params(nb, mode=nb.NB_FP64, **big)
+    p64 = _params(nb, mode=nb.NB_FP64, law=nb.NB_LAW_PAPER, eps=0.001, gamma=1.0, beta=0.5,
+                  **big)
     assert nb.nb_scratch_bytes(p64) - nb.nb_scratch_bytes(b64) == 3 * (-(-slots * 8 // 256) * 256)
 
 
