@@ -57,10 +57,6 @@ constexpr int TJ = 256;          // j elements staged in LDS per tile (one per t
 constexpr int KI32 = NB_KI32;    // i elements per lane, FP32 force kernel
 constexpr int KI64 = 1;          // i elements per lane, FP64 force kernel
 constexpr int SYM_ROWS = NB_SYM_ROWS;  // tile rows per block of the symmetric kernel
-// Small systems have too few (row group, chunk) units to fill the chip; their units are split
-// four ways by the 64-element j groups of each tile (one group of every tile per unit).
-constexpr int QSPLIT_SMALL = 4;
-constexpr int QSPLIT_MAX_UNITS = 1024;  // split when a system has fewer units than this
 // The FP64 mode uses the symmetric scheme too (k_force_sym64), with one tile row per block; a
 // build with two rows per block keeps the one-sided FP64 kernel.
 #ifndef NB_FP64_SYM
@@ -145,8 +141,7 @@ struct SysDesc {
     float *react;
     int32_t ch, sym;      // tiles per chunk; 1 when the symmetric kernel is used
     void *vxs, *vys, *vzs;  // sorted velocities (eqs. 4-6 only; null otherwise)
-    int32_t law;
-    int32_t qsplit;       // symmetric FP32 kernel: units per (row group, chunk), 1 or QSPLIT_SMALL
+    int32_t law, pad3;
 };
 
 // Kernel argument describing one launch over a segment table.

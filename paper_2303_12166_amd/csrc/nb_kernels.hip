@@ -469,12 +469,12 @@ __device__ __forceinline__ float pair_s(float r2, float w, float dx, float dy, f
 template <int LAW>
 __device__ __forceinline__ void diag_tile(const float4 *__restrict__ sj,
                                           const float4 *__restrict__ sv, IState<1> &I,
-                                          const float4 &vi, const LawF &K, int j0, int j1)
+                                          const float4 &vi, const LawF &K)
 {
     const float eps = 1.0e-24f;
     const int self = threadIdx.x;
 #pragma unroll 4
-    for (int jj = j0; jj < j1; ++jj) {
+    for (int jj = 0; jj < TJ; ++jj) {
         const float4 P = sj[sym_slot(jj)];
         const float dx = P.x - I.x[0];
         const float dy = P.y - I.y[0];
@@ -494,26 +494,23 @@ __device__ __forceinline__ void diag_tile(const float4 *__restrict__ sj,
     }
 }
 
-// NG = 4 covers the tile's four 64-element groups; NG = 1 only group gq (split units).
-template <bool NEAR, int LAW, int NG>
+template <bool NEAR, int LAW>
 __device__ __forceinline__ void sym_tile(const float4 *__restrict__ sj,
                                          const float4 *__restrict__ sv, IState<1> &I,
                                          const float4 &vi, const LawF &K, float *rwx, float *rwy,
-                                         float *rwz, int lane, int gq)
+                                         float *rwz, int lane)
 {
     // keep p = s d and the rotated update a_j <- rotate(a_j) - p as separate operations, so that
     // the rotation folds into the subtraction (a VOP2 instruction with a DPP source)
 #pragma clang fp contract(off)
     const float eps = 1.0e-24f;
-    float ajx[NG], ajy[NG], ajz[NG];
-#pragma unroll
-    for (int k = 0; k < NG; ++k) ajx[k] = ajy[k] = ajz[k] = 0.f;
+    float ajx[4] = {0.f, 0.f, 0.f, 0.f}, ajy[4] = {0.f, 0.f, 0.f, 0.f};
+    float ajz[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll NB_SYM_UNROLL
     for (int st = 0; st < 64; ++st) {
         const int e = NB_SYM_DUP ? lane + 64 - st : (lane - st) & 63;
 #pragma unroll
-        for (int k = 0; k < NG; ++k) {
-            const int g = NG == 4 ? k : gq;
+        for (int g = 0; g < 4; ++g) {
             const float4 P = sj[g * SYM_GSTRIDE + e];
             const float dx = P.x - I.x[0];
             const float dy = P.y - I.y[0];
@@ -530,18 +527,17 @@ __device__ __forceinline__ void sym_tile(const float4 *__restrict__ sj,
             I.ax[0] += px;
             I.ay[0] += py;
             I.az[0] += pz;
-            ajx[k] = wave_ror1(ajx[k]) - px;
-            ajy[k] = wave_ror1(ajy[k]) - py;
-            ajz[k] = wave_ror1(ajz[k]) - pz;
+            ajx[g] = wave_ror1(ajx[g]) - px;
+            ajy[g] = wave_ror1(ajy[g]) - py;
+            ajz[g] = wave_ror1(ajz[g]) - pz;
         }
     }
 #pragma unroll
-    for (int k = 0; k < NG; ++k) {
+    for (int g = 0; g < 4; ++g) {
         // one more rotation brings element l's sum back to lane l
-        const int g = NG == 4 ? k : gq;
-        rwx[g * 64 + lane] = wave_ror1(ajx[k]);
-        rwy[g * 64 + lane] = wave_ror1(ajy[k]);
-        rwz[g * 64 + lane] = wave_ror1(ajz[k]);
+        rwx[g * 64 + lane] = wave_ror1(ajx[g]);
+        rwy[g * 64 + lane] = wave_ror1(ajy[g]);
+        rwz[g * 64 + lane] = wave_ror1(ajz[g]);
     }
 }
 
@@ -591,19 +587,10 @@ __device__ __forceinline__ size_t react_group_offset(int g, int ntiles)
 // i per lane). Each j tile t of the chunk is staged once in LDS for all rows; row I evaluates
 // t = I one-sided, t > I with reactions, and skips t < I. The reactions of all rows on tile t
 // are added (rows in order, waves in order within a row) and stored once per (group, tile).
-//
-// A small system's units are split by j group (S.qsplit = QSPLIT_SMALL): unit (g, c Q + q) takes
-// only the 64-element group q of every tile of chunk c, so it stores the reactions of that group
-// and its own i partial, chunk-partial slot c Q + q.
 template <int LAW>
-__device__ void force_unit_sym(const SysDesc &S, int grp, int cq, float4 *sj, float4 *sv,
+__device__ void force_unit_sym(const SysDesc &S, int grp, int c, float4 *sj, float4 *sv,
                                float (*rw)[3][TJ])
 {
-    // unit-wide values, held in scalar registers; only the contact-law kernel splits units (a
-    // larger eqs. (4)-(6) kernel with the split variants measured 3.7 % slower on every system)
-    const int Q = LAW == 0 ? __builtin_amdgcn_readfirstlane(S.qsplit) : 1;
-    const int c = __builtin_amdgcn_readfirstlane(Q == 1 ? cq : cq / Q);
-    const int gq = __builtin_amdgcn_readfirstlane(cq - c * Q);  // the unit's j group when split
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = tid / TJ, lt = tid % TJ;
     const float *__restrict__ XS = static_cast<const float *>(S.xs);
@@ -708,7 +695,7 @@ __device__ void force_unit_sym(const SysDesc &S, int grp, int cq, float4 *sj, fl
         K.gc = Ka.gc;
         K.gcb = Ka.gcb;
         if (row_ok && t == I) {
-            diag_tile<LAW>(sj, sv, Ist, vi, K, Q == 1 ? 0 : 64 * gq, Q == 1 ? TJ : 64 * gq + 64);
+            diag_tile<LAW>(sj, sv, Ist, vi, K);
         } else if (row_ok && t > I) {
             const float *bx = S.tbox + (size_t)t * 8;
             const float gx = fmaxf(0.0f, fmaxf(bx[0] - hi[0], lo[0] - bx[4]));
@@ -716,28 +703,18 @@ __device__ void force_unit_sym(const SysDesc &S, int grp, int cq, float4 *sj, fl
             const float gz = fmaxf(0.0f, fmaxf(bx[2] - hi[2], lo[2] - bx[6]));
             const float gap2 = gx * gx + gy * gy + gz * gz;
             const int far = __builtin_amdgcn_readfirstlane(gap2 >= (jstar ? far2b : far2a) ? 1 : 0);
-            if (Q == 1) {
-                if (far) {
-                    sym_tile<false, LAW, 4>(sj, sv, Ist, vi, K, rw[wave][0], rw[wave][1],
-                                            rw[wave][2], lane, 0);
-                } else {
-                    sym_tile<true, LAW, 4>(sj, sv, Ist, vi, K, rw[wave][0], rw[wave][1],
-                                           rw[wave][2], lane, 0);
-                }
-            } else if constexpr (LAW == 0) {
-                if (far) {
-                    sym_tile<false, LAW, 1>(sj, sv, Ist, vi, K, rw[wave][0], rw[wave][1],
-                                            rw[wave][2], lane, gq);
-                } else {
-                    sym_tile<true, LAW, 1>(sj, sv, Ist, vi, K, rw[wave][0], rw[wave][1],
-                                           rw[wave][2], lane, gq);
-                }
+            if (far) {
+                sym_tile<false, LAW>(sj, sv, Ist, vi, K, rw[wave][0], rw[wave][1], rw[wave][2],
+                                     lane);
+            } else {
+                sym_tile<true, LAW>(sj, sv, Ist, vi, K, rw[wave][0], rw[wave][1], rw[wave][2],
+                                    lane);
             }
         }
         if (t > g0) {
             // tile t lies after the group's first row, so at least one row left reactions
             __syncthreads();
-            if (tid < TJ && (Q == 1 || (lt >> 6) == gq)) {
+            if (tid < TJ) {
                 const size_t at = roff + (size_t)(t - g0 - 1) * TJ + lt;
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
@@ -762,7 +739,7 @@ __device__ void force_unit_sym(const SysDesc &S, int grp, int cq, float4 *sj, fl
     if (real) {
         float *P = static_cast<float *>(S.part);
         const size_t na = S.nalloc;
-        const size_t b = (size_t)cq * 3 * na + slot;
+        const size_t b = (size_t)c * 3 * na + slot;
         P[b] = sumx - cx;
         P[b + na] = sumy - cy;
         P[b + 2 * na] = sumz - cz;
@@ -814,7 +791,7 @@ __global__ __launch_bounds__(BT * SEGS) void k_combine_sym(Launch L)
         const float *R = S.react;
         const size_t na = S.nalloc;
         const int own = J / SYM_ROWS;                        // the element's own group
-        const int cj = (T - SYM_ROWS * own + S.ch - 1) / S.ch * S.qsplit;  // its chunk partials
+        const int cj = (T - SYM_ROWS * own + S.ch - 1) / S.ch;  // its chunk count
         const int ng = (J + SYM_ROWS - 1) / SYM_ROWS;          // groups with a row before J
         const int r0 = (int)(((int64_t)ng * k) / SEGS), r1 = (int)(((int64_t)ng * (k + 1)) / SEGS);
         float out[3] = {0.f, 0.f, 0.f};
@@ -822,20 +799,8 @@ __global__ __launch_bounds__(BT * SEGS) void k_combine_sym(Launch L)
             for (int d = 0; d < 3; ++d) {
                 float sum = 0.f, comp = 0.f;
                 if (k == 0) {
-                    const float *Pd = P + (size_t)d * na + slot;
-                    int c = 0;
-                    if (S.qsplit > 1) {
-                        // a small system has few threads to hide load latency behind, and four
-                        // partials per chunk: read them eight at a time, added in chunk order
-                        for (; c + 8 <= cj; c += 8) {
-                            float v[8];
-#pragma unroll
-                            for (int q = 0; q < 8; ++q) v[q] = Pd[(size_t)(c + q) * 3 * na];
-#pragma unroll
-                            for (int q = 0; q < 8; ++q) kahan_add(sum, comp, v[q]);
-                        }
-                    }
-                    for (; c < cj; ++c) kahan_add(sum, comp, Pd[(size_t)c * 3 * na]);
+                    for (int c = 0; c < cj; ++c)
+                        kahan_add(sum, comp, P[(size_t)c * 3 * na + d * na + slot]);
                 }
                 // groups are read eight at a time (independent loads in flight), then added in
                 // group order; the arithmetic is the same as one group at a time

@@ -48,7 +48,6 @@ struct TileCfg {
     int ki, nsplit, iblock, jchunk, n_iblocks, n_units, n_ounits;
     int npad, p1, nalloc, ntiles;
     int sym, ch;            // symmetric kernel (Kahan and FP64 modes) and its tiles per chunk
-    int q;                  // units per (row group, chunk): 1, or QSPLIT_SMALL for small systems
     size_t react_floats;    // reaction partials of the symmetric kernel (elements of the mode's type)
 };
 
@@ -63,10 +62,9 @@ std::vector<Override> g_overrides;
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 // Sorted layout and work split of a system; a function of (n, n1, mode) and the overrides only.
-TileCfg tile_config(int64_t n, int64_t n1, int mode, int law = NB_LAW_CONTACT)
+TileCfg tile_config(int64_t n, int64_t n1, int mode)
 {
     TileCfg c{};
-    c.q = 1;
     c.ki = mode == NB_FP64 ? KI64 : KI32;
     c.iblock = BT * c.ki;
     c.p1 = (int)round_up(n1, TJ);
@@ -100,12 +98,6 @@ TileCfg tile_config(int64_t n, int64_t n1, int mode, int law = NB_LAW_CONTACT)
             units += (span + c.ch - 1) / c.ch;
             react_tiles += span - 1;
         }
-        // a small FP32 Kahan system under the contact law splits each unit by the tiles'
-        // 64-element j groups
-        c.q = mode == NB_FP32_KAHAN && law == NB_LAW_CONTACT && units < QSPLIT_MAX_UNITS
-                  ? QSPLIT_SMALL
-                  : 1;
-        units *= c.q;
         // far beyond any device's memory the unit count no longer fits int32: n_units = -1
         // makes nb_scratch_bytes and nb_create report NB_E_NOMEM
         c.n_units = units > INT32_MAX ? -1 : (int)units;
@@ -153,7 +145,7 @@ Layout layout_for(int mode, int law, const TileCfg &c)
     L.units = take(c.sym ? (size_t)c.n_units * 2 * sizeof(int32_t) : 0);
     L.react = take(c.sym ? c.react_floats * elem : 0);
     L.part = off;
-    if (c.nsplit > 1 || c.sym) take((size_t)c.nsplit * c.q * 3 * (size_t)c.nalloc * elem);
+    if (c.nsplit > 1 || c.sym) take((size_t)c.nsplit * 3 * (size_t)c.nalloc * elem);
     L.total = off;
     return L;
 }
@@ -466,7 +458,7 @@ int nb_tile_override(int64_t n_lo, int64_t n_hi, int32_t nsplit)
 int nb_scratch_bytes(const nb_params *p, size_t *out)
 {
     if (!params_ok(p) || !out) return NB_E_INVAL;
-    TileCfg c = tile_config(p->n, p->n1, p->mode, p->law);
+    TileCfg c = tile_config(p->n, p->n1, p->mode);
     if (c.n_units < 0) return NB_E_NOMEM;
     *out = layout_for(p->mode, p->law, c).total;
     return NB_OK;
@@ -486,7 +478,7 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
         if (!b->side) return NB_E_INVAL;
     }
     if (!b->scratch || !aligned(b->scratch, ALIGN)) return NB_E_INVAL;
-    TileCfg cfg = tile_config(p->n, p->n1, p->mode, p->law);
+    TileCfg cfg = tile_config(p->n, p->n1, p->mode);
     if (cfg.n_units < 0) return NB_E_NOMEM;
     Layout lay = layout_for(p->mode, p->law, cfg);
     if (b->scratch_bytes < lay.total) return NB_E_NOMEM;
@@ -538,7 +530,6 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
     d.vys = paper ? base + lay.vys : nullptr;
     d.vzs = paper ? base + lay.vzs : nullptr;
     d.law = p->law;
-    d.qsplit = cfg.q;
     d.perm = reinterpret_cast<int32_t *>(base + lay.perm);
     d.tbox = reinterpret_cast<float *>(base + lay.tbox);
     d.npad = cfg.npad;
@@ -640,7 +631,7 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
                 const int chunks = (span + cfg.ch - 1) / cfg.ch;
                 for (int c = 0; c < chunks; ++c) {
                     const int len = std::min(cfg.ch, span - c * cfg.ch);
-                    for (int q = 0; q < cfg.q; ++q) order.push_back({-len, {g, c * cfg.q + q}});
+                    order.push_back({-len, {g, c}});
                 }
             }
             std::stable_sort(order.begin(), order.end(),
