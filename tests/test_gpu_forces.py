@@ -134,20 +134,36 @@ def test_repeated_evaluation_is_bitwise_stable():
     s.close()
 
 
+@pytest.mark.parametrize("mode,tol", [("kahan", 1e-5), ("fp64", 1e-12)])
 @pytest.mark.parametrize("nsplit", [1, 2, 3, 7])
-def test_j_split_choices_agree(nsplit):
+def test_j_split_choices_agree(nsplit, mode, tol):
+    """Every chunking of the symmetric kernels (FP32 Kahan and FP64) gives oracle parity."""
     nb = require_gpu()
     n = 12345
     ic = synth.make_binary(n, 0.6, seed=2)
     nb.nb_tile_override(n, n, nsplit)
     try:
-        cfg = nb.nb_tile_config(n, ic.n1, nb.NB_FP32_KAHAN)
-        print_case("nsplit", nsplit, cfg)
-        a = _gpu_forces(nb, ic, "kahan")
+        cfg = nb.nb_tile_config(n, ic.n1, nb.MODES[mode])
+        print_case("nsplit", nsplit, mode, cfg)
+        a = _gpu_forces(nb, ic, mode)
     finally:
         nb.nb_tile_override(n, n, 0)
-    ref = oracle.accel(_oracle_input(ic, "kahan"), ic.n1, ic.G, ic.m, ic.D1, ic.D2)
-    assert force_error(a, ref) <= 1e-5
+    ref = oracle.accel(_oracle_input(ic, mode), ic.n1, ic.G, ic.m, ic.D1, ic.D2)
+    assert force_error(a, ref) <= tol
+
+
+def test_full_size_sampled_rows_fp64():
+    """The FP64 symmetric kernel at N = 262,144 (q = 0.3) on sampled rows."""
+    nb = require_gpu()
+    n, q = 262144, 0.3
+    ic = synth.make_binary(n, q, seed=0)
+    print_case("full size sampled fp64", n, q)
+    a = _gpu_forces(nb, ic, "fp64")
+    rows = sample_rows(n, ic.n1, 96, seed=n + 1)
+    ref = oracle.accel(_oracle_input(ic, "fp64"), ic.n1, ic.G, ic.m, ic.D1, ic.D2, rows=rows)
+    err = force_error(a[rows], ref)
+    print("full size fp64 max rel err", err)
+    assert err <= 1e-12
 
 
 @pytest.mark.parametrize("blocks", [7, 512])
