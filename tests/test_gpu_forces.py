@@ -167,13 +167,15 @@ def test_full_size_sampled_rows_fp64():
 
 
 @pytest.mark.parametrize("blocks", [7, 512])
-def test_persistent_launch_is_bitwise_identical(blocks):
+@pytest.mark.parametrize("mode", ["kahan", "fp64"])
+def test_persistent_launch_is_bitwise_identical(blocks, mode):
     nb = require_gpu()
+    print_case("persistent grid", blocks, mode)
     ic = synth.make_binary(30000, 0.5, seed=4)
-    a0 = _gpu_forces(nb, ic, "kahan")
+    a0 = _gpu_forces(nb, ic, mode)
     nb.nb_set_force_grid(blocks)
     try:
-        a1 = _gpu_forces(nb, ic, "kahan")
+        a1 = _gpu_forces(nb, ic, mode)
     finally:
         nb.nb_set_force_grid(0)
     assert np.array_equal(a0, a1)
