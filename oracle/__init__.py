@@ -11,7 +11,9 @@ Pins (tests/test_oracle_*.py): pair-law closed forms (continuity at D, zero at 1
 limit), Newton far field, dU/dr = f by finite differences, exact antisymmetry and momentum
 conservation, two-body Kepler orbits (circular and eccentric, via Kepler's equation), second-order
 energy error of the leap-frog, eq. (3) limits, the L1 root's symmetry and Hill limit, the donor
-growth stop step in closed form, and hand-placed L1 counts.
+growth stop step in closed form, and hand-placed L1 counts; under eqs. (4)-(6) the lens
+volume (closed form and Monte Carlo), elastic and inelastic head-on collisions, and the potential
+energy sum against hand-integrated contact energies and a quadrature of the lens volume.
 """
 
 from __future__ import annotations

@@ -188,3 +188,109 @@ def test_force_in_a_step_sees_the_half_step_velocity(orc):
     run.advance(1)
     assert np.allclose(run.pos, x1, rtol=0, atol=1e-15)
     assert np.allclose(run.vel, v1, rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------------------------ potential energy sum, eqs. (5)-(6)
+#
+# The contact energy of a pair is the work done against the overlap repulsion from first touch
+# (r = 2R) down to r: gamma * integral_r^2R V(s) ds. The hand values below come from integrating
+# the lens volume V(s) = pi (4/3 R^3 - R^2 s + s^3/12) by hand:
+#   r = 0: R^4,  r = R/2: 117/256 R^4,  r = R: 7/48 R^4,  r = 3R/2: 5/256 R^4,  r >= 2R: 0
+# (each times gamma pi), plus the softened gravity -G m^2 / (r + eps).
+
+PE_EPS, PE_GAMMA = 0.004, 3.0e3
+
+
+def _pe_two(orc, r, D1=2 * R, D2=2 * R, n1=2):
+    pos = np.array([[0.1, -0.2, 0.05], [0.1 + r, -0.2, 0.05]])
+    return orc.paper_pe(pos, n1, G, M, D1, D2, PE_EPS, PE_GAMMA)
+
+
+@pytest.mark.parametrize("frac,contact", [(0.5, 117 / 256), (1.0, 7 / 48), (1.5, 5 / 256),
+                                          (2.5, 0.0), (4.0, 0.0)])
+def test_paper_pe_two_elements_hand_values(orc, frac, contact):
+    r = frac * R
+    want = -G * M * M / (r + PE_EPS) + contact * PE_GAMMA * math.pi * R**4
+    assert _pe_two(orc, r) == pytest.approx(want, rel=1e-12)
+
+
+def test_paper_pe_continuous_at_contact_and_full_overlap_limit(orc):
+    # just inside contact the overlap energy vanishes like (2R - r)^3
+    for r in (2 * R * (1 - 1e-6), 2 * R * (1 + 1e-6)):
+        assert _pe_two(orc, r) == pytest.approx(-G * M * M / (r + PE_EPS), rel=1e-12)
+    # nearly full overlap: gamma pi R^4 of contact energy
+    tiny = 1e-9 * R
+    assert _pe_two(orc, tiny) == pytest.approx(
+        -G * M * M / (tiny + PE_EPS) + PE_GAMMA * math.pi * R**4, rel=1e-7)
+
+
+def test_paper_pe_uses_half_the_pair_diameter_per_star_class(orc):
+    # D1 != D2: inside star 1 R = D1/2, inside star 2 R = D2/2, across R = (D1 + D2)/4
+    D1, D2 = 0.1, 0.06
+    for n1, Rp in ((2, D1 / 2), (0, D2 / 2), (1, (D1 + D2) / 4)):
+        got = _pe_two(orc, Rp, D1=D1, D2=D2, n1=n1)
+        want = -G * M * M / (Rp + PE_EPS) + 7 / 48 * PE_GAMMA * math.pi * Rp**4
+        assert got == pytest.approx(want, rel=1e-12), n1
+
+
+def test_paper_pe_collinear_triple_counts_each_pair_once(orc):
+    # elements at 0, R and 5R/2 on a line: pair distances R, 3R/2 and 5R/2
+    pos = np.array([[0.0, 0.0, 0.0], [R, 0.0, 0.0], [2.5 * R, 0.0, 0.0]])
+    got = orc.paper_pe(pos, 3, G, M, 2 * R, 2 * R, PE_EPS, PE_GAMMA)
+    want = (-G * M * M * (1 / (R + PE_EPS) + 1 / (1.5 * R + PE_EPS) + 1 / (2.5 * R + PE_EPS))
+            + (7 / 48 + 5 / 256) * PE_GAMMA * math.pi * R**4)
+    assert got == pytest.approx(want, rel=1e-12)
+
+
+def _contact_energy_quadrature(r, Rp):
+    """gamma * integral_r^2R V(s) ds with V from the lens formula pi (4R + s)(2R - s)^2 / 12
+    (a cubic, so two-point Gauss-Legendre is exact)."""
+    lo, hi = r, np.maximum(2 * Rp, r)
+    mid, half = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    out = 0.0
+    for t in (-1 / math.sqrt(3), 1 / math.sqrt(3)):
+        s = mid + half * t
+        out = out + half * math.pi * (4 * Rp + s) * (2 * Rp - s) ** 2 / 12
+    return PE_GAMMA * out
+
+
+def test_paper_pe_random_cluster_against_quadrature(orc):
+    """Every pair of a dense two-star cluster (many contacts), written out pair by pair with the
+    contact energy from quadrature of the lens volume."""
+    rng = np.random.default_rng(21)
+    n, n1, D1, D2 = 60, 35, 0.08, 0.05
+    pos = rng.uniform(-0.12, 0.12, size=(n, 3))
+    want = 0.0
+    contacts = 0
+    for i in range(n):
+        for j in range(i + 1, n):
+            r = float(np.linalg.norm(pos[j] - pos[i]))
+            si, sj = i >= n1, j >= n1
+            D = (D1 + D2) / 2 if si != sj else (D2 if si else D1)
+            want += -G * M * M / (r + PE_EPS)
+            if r < D:
+                want += _contact_energy_quadrature(r, D / 2)
+                contacts += 1
+    assert contacts > 50
+    got = orc.paper_pe(pos, n1, G, M, D1, D2, PE_EPS, PE_GAMMA)
+    assert got == pytest.approx(want, rel=1e-12)
+
+
+def test_paper_pe_conserved_in_elastic_head_on_collision(orc):
+    """With beta = 1 the law is conservative: KE + paper_pe stays constant through the bounce up
+    to the leap-frog's O(dt^2) error, and it is the same energy the pair potential gives."""
+    gamma, eps, Gs = 2000.0, 1e-4, 1e-6
+    pos = np.array([[-2 * R, 0.0, 0.0], [2 * R, 0.0, 0.0]])
+    vel = np.array([[1.0, 0.0, 0.0], [-1.0, 0.0, 0.0]])
+    run = orc.Run(pos, vel, 2, Gs, M, 2e-4, 2 * R, 2 * R, 1.0, growth_on=False, law=1, eps=eps,
+                  gamma=gamma, beta=1.0)
+    energies, min_r = [], 4 * R
+    for _ in range(40):
+        run.advance(100)
+        p, v = run.pos, run.vel
+        min_r = min(min_r, float(np.linalg.norm(p[1] - p[0])))
+        energies.append(0.5 * M * (v * v).sum() + orc.paper_pe(p, 2, Gs, M, 2 * R, 2 * R, eps,
+                                                                 gamma))
+    E0 = 0.5 * M * (vel * vel).sum() + orc.paper_pe(pos, 2, Gs, M, 2 * R, 2 * R, eps, gamma)
+    assert min_r < 1.5 * R  # the pair went deep into contact
+    assert np.abs(np.array(energies) - E0).max() < 2e-3 * abs(E0)
