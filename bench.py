@@ -11,6 +11,12 @@ roofline position (20 flops per interaction, measured with HIP events on the lau
 the FP64 CPU oracle's rate on a bounded row sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--workload c3|c2|c4] [--mode kahan|plain|fp64]
+                    [--serve full|small|none]
+
+The same line carries the serving measurement (by default the 256-request trace: continuous
+batching against one-at-a-time solves, sims/s and p50/p99 latency both ways, whether every final
+state is bitwise the same both ways, and the step-0 force error against the oracle of one request
+per size decile).
 """
 
 from __future__ import annotations
@@ -29,10 +35,16 @@ if ROOT not in sys.path:
 
 METRIC = "pair interactions/s + % FP32 VALU peak at N=256K; served sims/s, p50/p99"
 FLOPS_PER_INTERACTION = 20
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 (packed FP32) x 2 (FMA) x 2.4 GHz
+# MI355X published vector peaks: 157.3 TFLOP/s FP32 and 78.6 TFLOP/s FP64. Over 256 CUs at
+# 2.4 GHz the FP32 figure is 256 flops per clock per CU, that is 128 FP32 FMA lane-operations per
+# clock per CU (the FP64 figure half of that). The library emits only non-packed FP32
+# instructions; how close a stream of them comes to 128 lanes per clock is measured on the part
+# itself by the issue-rate probe (nb_valu_probe), reported beside the roofline.
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
-VALU_LANE_ISSUE_PER_S = 256 * 128 * 2.4e9  # non-packed VALU lane-instructions per second
+N_CU, CLOCK_HZ = 256, 2.4e9
+FMA_LANES_PER_CLK_CU = PEAK_FP32_TFLOPS * 1e12 / (2 * N_CU * CLOCK_HZ)  # 128
+VALU_LANE_ISSUE_PER_S = FMA_LANES_PER_CLK_CU * N_CU * CLOCK_HZ
 
 WORKLOADS = {
     "c3": dict(n=262144, q=0.3, mode="kahan", steps=200, warmup=5),
@@ -166,6 +178,31 @@ def oracle_scaling(cores: int) -> dict:
     return out
 
 
+def valu_probe() -> dict:
+    """Measured issue rates of single VALU instruction streams (lane-instructions per clock per
+    CU at the 2.4 GHz peak clock): 2048 blocks of 256 lanes (eight waves per SIMD), eight
+    independent chains per lane."""
+    import torch
+
+    import paper_2303_12166_amd as nb
+
+    sink = torch.zeros(64, dtype=torch.float32, device="cuda")
+    blocks = N_CU * 4 * 8 // 4
+    out = {}
+    for op, name, iters in ((0, "v_fma_f32", 65536), (1, "v_rsq_f32", 16384),
+                            (2, "v_rcp_f32", 16384), (3, "3 v_fma_f32 + 1 v_rsq_f32", 16384)):
+        nb.nb_valu_probe(op, blocks, 64, sink)
+        best = None
+        for _ in range(3):
+            ms, ops = nb.nb_valu_probe(op, blocks, iters, sink)
+            rate = ops / (ms * 1e-3) / (N_CU * CLOCK_HZ)
+            best = rate if best is None else max(best, rate)
+        out[name] = round(best, 2)
+    out["unit"] = "lane-instructions per clock per CU (2.4 GHz, 256 CUs)"
+    out["published_fma_lanes_per_clk_cu"] = FMA_LANES_PER_CLK_CU
+    return out
+
+
 def copy_calibration() -> int:
     import torch
 
@@ -180,10 +217,8 @@ def copy_calibration() -> int:
     return 0
 
 
-def serving(scale: str) -> dict:
-    """Continuous batching vs one-at-a-time plain solves on one Poisson request trace."""
+def serving_trace(scale: str):
     import synth
-    from paper_2303_12166_amd import serve
 
     if scale == "full":
         trace = synth.make_trace()  # 256 requests, 20/s, N 4096..131072, q 0.1..1, 500 steps
@@ -192,6 +227,67 @@ def serving(scale: str) -> dict:
         trace = synth.make_trace(count=48, rate=200.0, n_max=32768, steps=200)
         desc = ("48 requests, Poisson 200/s, N log-uniform 4096..32768 (x64), q U[0.1,1], "
                 "200 steps")
+    return trace, desc
+
+
+def served_sample(trace, k: int = 10):
+    """One request per size decile of the trace (the median-N request of each tenth)."""
+    order = sorted(trace, key=lambda r: (r.n, r.rid))
+    out = []
+    for d in range(k):
+        lo, hi = d * len(order) // k, (d + 1) * len(order) // k
+        if hi > lo:
+            out.append(order[(lo + hi) // 2])
+    return out
+
+
+def served_reference(sample, rows_per_request: int = 64):
+    """CPU-baseline leg: the FP64 oracle's step-0 accelerations on sampled rows of each sampled
+    request (the request's own seeded system)."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    refs = []
+    t0 = time.perf_counter()
+    for req in sample:
+        ic = synth.make_binary(req.n, req.q, seed=req.seed)
+        rows = np.unique(np.concatenate([[0, ic.n1 - 1, ic.n1, ic.n - 1],
+                                         np.linspace(0, ic.n - 1, rows_per_request)]
+                                        ).astype(np.int64))
+        p, _ = ic.f32_as_f64()
+        refs.append((rows, oracle.accel(p, ic.n1, ic.G, ic.m, ic.D1, ic.D2, rows=rows)))
+    log("oracle reference of %d served requests: %.1f s" % (len(sample), time.perf_counter() - t0))
+    return refs
+
+
+def served_errors(sample, refs) -> dict:
+    """Step-0 force error of each sampled request's system on the GPU (the arithmetic the server
+    runs: a system's kernels and work split depend on its own size only) against the oracle."""
+    import numpy as np
+
+    import paper_2303_12166_amd as nb
+    import synth
+
+    rows_out, worst = [], 0.0
+    for req, (rows, ref) in zip(sample, refs):
+        s = nb.System.from_ic(synth.make_binary(req.n, req.q, seed=req.seed), mode="kahan")
+        a = s.accelerations()
+        s.close()
+        err = float(np.linalg.norm(a[rows] - ref, axis=1).max() / np.linalg.norm(ref, axis=1).max())
+        worst = max(worst, err)
+        rows_out.append({"rid": req.rid, "n": req.n, "q": round(req.q, 4), "rows": int(len(rows)),
+                         "force_error_step0": err})
+    return {"metric": "max_i |a_gpu-a_oracle| / max_k |a_oracle| on sampled rows, one request "
+                      "per size decile", "requests": rows_out, "max": worst}
+
+
+def serving(scale: str) -> dict:
+    """Continuous batching vs one-at-a-time plain solves on one Poisson request trace."""
+    from paper_2303_12166_amd import serve
+
+    trace, desc = serving_trace(scale)
     budget = 64 << 30
     server = serve.BatchServer(budget_bytes=budget, round_steps=10)
     t0 = time.perf_counter()
@@ -199,18 +295,20 @@ def serving(scale: str) -> dict:
     log("batched run %.1f s (%d rounds, %d graphs)" % (time.perf_counter() - t0, server.rounds,
                                                       server.graphs_built))
     t0 = time.perf_counter()
-    seq = serve.run_sequential(trace)
+    seq = serve.run_sequential(trace, log=log if scale == "full" else None)
     log("sequential run %.1f s" % (time.perf_counter() - t0))
     sb, ss = serve.summarize(batched), serve.summarize(seq)
     same = all(a.digest == b.digest for a, b in zip(batched, seq))
     return {
         "trace": desc,
+        "requests": len(trace),
         "budget_bytes": budget,
         "round_steps": server.round_steps,
         "batched": sb,
         "sequential": ss,
         "sims_per_s_speedup": sb["sims_per_s"] / ss["sims_per_s"],
         "results_identical": same,
+        "evicted_nonfinite": server.evicted,
     }
 
 
@@ -336,9 +434,12 @@ def main() -> int:
                          "synth.paper_law_params; Kahan or FP64 only)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--serve", choices=["none", "small", "full"], default="small",
-                    help="serving measurement: 'small' adds a 48-request trace to the main line; "
-                         "'full' runs only the 256-request trace (N 4096..131072, 500 steps)")
+    ap.add_argument("--serve", choices=["none", "small", "full"], default="full",
+                    help="serving measurement added to the main line: 'full' (default) the "
+                         "256-request trace (Poisson 20/s, N 4096..131072, 500 steps), 'small' a "
+                         "48-request trace (N 4096..32768, 200 steps), 'none' no serving")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="print only the serving measurement (--serve picks the trace)")
     ap.add_argument("--precision-study", action="store_true",
                     help="N=131072, q=0.8: FP32 plain, FP32 Kahan and FP64 runs of --steps steps "
                          "(default 2000), step-0 force error vs the FP64 oracle and FP64 drift of "
@@ -379,14 +480,14 @@ def main() -> int:
                           "value": None, "n_gpus": 1, "data": "synthetic", "lobe_fill": res}),
               flush=True)
         return 0
-    if args.serve == "full":
+    if args.serve_only:
         import torch
 
         import paper_2303_12166_amd as nb
 
         nb.load()
         torch.cuda.set_device(0)
-        res = serving("full")
+        res = serving("small" if args.serve == "small" else "full")
         print(json.dumps({
             "metric": METRIC, "value": res["batched"]["sims_per_s"], "unit": "sims/s",
             "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f32",
@@ -455,6 +556,11 @@ def main() -> int:
     peak = PEAK_FP64_TFLOPS if mode == "fp64" else PEAK_FP32_TFLOPS
     counters = counter_record(args.workload + (":paper" if law else ""), mode, cfg["nsplit"])
     achieved = FLOPS_PER_INTERACTION * inter / avg_s / 1e12 if avg_s > 0 else 0.0
+    kernel = (PAPER_KERNEL_NAMES if law else KERNEL_NAMES)[mode]
+    # pairs the kernel evaluates: N^2 / 2 with the symmetric kernels (each unordered pair once),
+    # N^2 one-sided
+    evaluated = inter / 2 if kernel.startswith("k_force_sym") else inter
+    executed = FLOPS_PER_INTERACTION * evaluated / avg_s / 1e12 if avg_s > 0 else 0.0
     roofline = {
         "bound": "alu",
         "achieved": round(achieved, 3),
@@ -462,16 +568,25 @@ def main() -> int:
         "unit": "TFLOP/s",
         "frac": round(achieved / peak, 4),
         "traffic": (counters or {}).get("bytes_per_launch"),
-        "kernel": (PAPER_KERNEL_NAMES if law else KERNEL_NAMES)[mode],
+        "kernel": kernel,
         "flops_per_interaction": FLOPS_PER_INTERACTION,
         "avg_launch_ms": round(avg_s * 1e3, 4),
         "launches": launches,
         "flops_per_launch": FLOPS_PER_INTERACTION * inter,
         "kernel_interactions_per_s": inter / avg_s if avg_s > 0 else 0.0,
+        # the convention above counts N^2 interactions per evaluation; the symmetric kernel
+        # evaluates each unordered pair once, so the work it executes is half that
+        "pairs_evaluated_per_launch": evaluated,
+        "executed_achieved": round(executed, 3),
+        "executed_frac": round(executed / peak, 4),
     }
+    probe = None
+    try:
+        probe = valu_probe()
+    except Exception as e:  # a probe failure must not lose the measurement
+        log("VALU probe failed: %s" % e)
+    roofline["valu_probe"] = probe
     if counters:
-        # pairs the kernel evaluates: N^2 / 2 with the symmetric kernel, N^2 one-sided
-        evaluated = inter / 2 if roofline["kernel"].startswith("k_force_sym") else inter
         vpp = counters.get("valu_lane_instructions_per_pair")
         roofline["counters"] = {
             "source": "profiles/force_counters.json (rocprofv3, same kernel source and split)",
@@ -481,11 +596,17 @@ def main() -> int:
             "algorithmic_bytes_per_launch": counters.get("algorithmic_bytes_per_launch"),
         }
         if vpp and avg_s > 0:
-            # achieved VALU issue (all VALU instructions, live timing) against the non-packed
-            # issue rate of 256 CUs x 128 lanes per clock x 2.4 GHz
+            # achieved VALU issue (every VALU instruction, transcendentals included, live timing)
+            # against 128 lane-instructions per clock per CU (the published FP32 peak in FMA
+            # lanes) and against the probe's measured non-packed FMA rate
             rate = vpp * evaluated / avg_s
             roofline["counters"]["valu_lane_instructions_per_s"] = rate
+            roofline["counters"]["valu_lane_instructions_per_clk_cu"] = round(
+                rate / (N_CU * CLOCK_HZ), 2)
             roofline["counters"]["valu_issue_frac"] = round(rate / VALU_LANE_ISSUE_PER_S, 4)
+            if probe and probe.get("v_fma_f32"):
+                roofline["counters"]["valu_issue_frac_of_probe_fma"] = round(
+                    rate / (N_CU * CLOCK_HZ) / probe["v_fma_f32"], 4)
 
     out = {
         "metric": METRIC,
@@ -523,16 +644,23 @@ def main() -> int:
     }
     s.close()
 
+    sample, refs = [], None
+    if args.serve != "none":
+        sample = served_sample(serving_trace(args.serve)[0])
     if not args.no_cpu:
         base, rows, ref = cpu_baseline(ic, args.cpu_seconds, law)
         out["cpu_baseline"] = base
         err = (np.linalg.norm(a0[rows] - ref, axis=1).max() / np.linalg.norm(ref, axis=1).max())
         out["force_error_step0"] = {"value": float(err), "rows": int(len(rows)),
                                     "metric": "max_i |a_gpu-a_oracle| / max_k |a_oracle|"}
+        if sample:
+            refs = served_reference(sample)
     else:
         out["cpu_baseline"] = None
-    if args.serve == "small":
-        out["serving"] = serving("small")
+    if args.serve != "none":
+        out["serving"] = serving(args.serve)
+        if refs is not None:
+            out["serving"]["oracle_check"] = served_errors(sample, refs)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -171,6 +171,16 @@ void nb_graph_destroy(nb_graph *g);
  * step saw a non-finite element. */
 int nb_diagnostics(nb_system *s, int32_t with_pe, nb_diag *out, void *stream);
 
+/* Health of running systems (Methodology: the element state is advanced step after step; a
+ * state that is no longer finite cannot be advanced further): queues on `stream` one copy per
+ * listed system of its non-finite element count after its last completed step (the value
+ * nb_diagnostics reports as `nonfinite`) into out_host[k] (int32, n_sys entries). Nothing is
+ * synchronised: the values are valid once `stream` has passed this call (an event recorded after
+ * it, or a stream synchronisation). With pinned host memory the copies are asynchronous; with
+ * pageable memory HIP may wait for them. Work that steps the systems on another stream must be
+ * ordered before this call by the caller (an event). NB_E_INVAL for null or foreign systems. */
+int nb_nonfinite_async(nb_system *const *sys, int32_t n_sys, int32_t *out_host, void *stream);
+
 /* Per-step L1 record of the most recent steps: up to max_steps rows of
  * {step, n_past, forward, backward}, oldest first, into out_host (int32, 4 per row). The library
  * keeps the last NB_L1_LOG_CAP steps. Synchronises `stream`. *n_out receives the row count. */
@@ -212,6 +222,16 @@ int nb_tile_override(int64_t n_lo, int64_t n_hi, int32_t nsplit);
  * units blockIdx, blockIdx + blocks, ... (a persistent launch). Results are bitwise the same
  * either way: a unit's arithmetic does not depend on which workgroup runs it. */
 int nb_set_force_grid(int32_t blocks);
+
+/* Measurement aid for the force kernels' roofline (no part of the model): times one launch of an
+ * issue-rate probe of the vector ALU on the current device and stream. Each of blocks x 256 lanes
+ * runs iters steps of eight independent dependency chains of one instruction: op 0 v_fma_f32,
+ * op 1 v_rsq_f32, op 2 v_rcp_f32, op 3 three v_fma_f32 per v_rsq_f32. *lane_ops receives the
+ * lane-instructions executed, *ms the kernel time (HIP events; synchronises `stream`). `sink` is
+ * a device buffer of at least 4 bytes that the probe may write (it keeps the chains live).
+ * NB_E_INVAL for a bad op, size or buffer. */
+int nb_valu_probe(int32_t op, int32_t blocks, int32_t iters, void *sink, void *stream, double *ms,
+                  int64_t *lane_ops);
 
 void nb_destroy(nb_system *s);
 const char *nb_strerror(int status);

@@ -151,6 +151,24 @@ def nb_diagnostics(handle: ctypes.c_void_p, with_pe: bool = False, stream=None) 
     }
 
 
+def nb_nonfinite_async(handles, out_host, stream=None) -> None:
+    """Queues copies of each system's non-finite count into ``out_host`` (an int32 tensor or
+    array with at least len(handles) entries, pinned for asynchrony); valid once ``stream`` has
+    passed the call."""
+    arr = (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h
+                                             for h in handles])
+    if hasattr(out_host, "data_ptr"):
+        if out_host.numel() < len(handles) or out_host.device.type != "cpu":
+            raise ValueError("out_host must be a host int32 tensor with one entry per system")
+        ptr = ctypes.cast(ctypes.c_void_p(out_host.data_ptr()), ctypes.POINTER(ctypes.c_int32))
+    else:
+        if out_host.dtype != np.int32 or out_host.size < len(handles):
+            raise ValueError("out_host must be an int32 array with one entry per system")
+        ptr = out_host.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    _check(load().nb_nonfinite_async(arr, len(handles), ptr, _stream(stream)),
+           "nb_nonfinite_async")
+
+
 def nb_retention(handle: ctypes.c_void_p, stream=None) -> tuple:
     """(n_past, n_bound): donor elements past L1 and those of them bound to the accretor."""
     past, bound = ctypes.c_int32(0), ctypes.c_int32(0)
@@ -212,6 +230,17 @@ def nb_graph_destroy(graph: ctypes.c_void_p) -> None:
 
 def nb_set_force_grid(blocks: int) -> None:
     _check(load().nb_set_force_grid(int(blocks)), "nb_set_force_grid")
+
+
+def nb_valu_probe(op: int, blocks: int, iters: int, sink, stream=None) -> tuple[float, int]:
+    """(kernel ms, lane-instructions executed) of one vector-ALU issue-rate probe launch;
+    ``sink`` is a device tensor of at least 4 bytes."""
+    ms = ctypes.c_double(0.0)
+    ops = ctypes.c_int64(0)
+    _check(load().nb_valu_probe(int(op), int(blocks), int(iters),
+                                ctypes.c_void_p(sink.data_ptr()), _stream(stream),
+                                ctypes.byref(ms), ctypes.byref(ops)), "nb_valu_probe")
+    return float(ms.value), int(ops.value)
 
 
 def nb_destroy(handle: ctypes.c_void_p) -> None:

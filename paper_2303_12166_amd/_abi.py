@@ -32,6 +32,7 @@ EXPORTED = (
     "nb_step",
     "nb_diagnostics",
     "nb_l1_log",
+    "nb_nonfinite_async",
     "nb_retention",
     "nb_timing_enable",
     "nb_timing_read",
@@ -39,6 +40,7 @@ EXPORTED = (
     "nb_tile_config",
     "nb_tile_override",
     "nb_set_force_grid",
+    "nb_valu_probe",
     "nb_graph_create",
     "nb_graph_launch",
     "nb_graph_destroy",
@@ -111,6 +113,7 @@ def declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.nb_step.argtypes = [P(_vp), _i32, _i32, _vp]
     lib.nb_diagnostics.argtypes = [_vp, _i32, P(NbDiag), _vp]
     lib.nb_l1_log.argtypes = [_vp, P(_i32), _i32, P(_i32), _vp]
+    lib.nb_nonfinite_async.argtypes = [P(_vp), _i32, P(_i32), _vp]
     lib.nb_retention.argtypes = [_vp, P(_i32), P(_i32), _vp]
     lib.nb_timing_enable.argtypes = [_i32]
     lib.nb_timing_read.argtypes = [P(ctypes.c_double), P(_i64)]
@@ -118,6 +121,7 @@ def declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.nb_tile_config.argtypes = [_i64, _i64, _i32, P(_i32), P(_i32), P(_i32), P(_i32)]
     lib.nb_tile_override.argtypes = [_i64, _i64, _i32]
     lib.nb_set_force_grid.argtypes = [_i32]
+    lib.nb_valu_probe.argtypes = [_i32, _i32, _i32, _vp, _vp, P(ctypes.c_double), P(_i64)]
     lib.nb_graph_create.argtypes = [P(_vp), _i32, _i32, _vp, P(_vp)]
     lib.nb_graph_launch.argtypes = [_vp, _vp]
     lib.nb_graph_destroy.argtypes = [_vp]

@@ -17,7 +17,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libnbody.so")
-SOURCES = [os.path.join(CSRC, "nb_kernels.hip"), os.path.join(CSRC, "nb_runtime.cpp")]
+SOURCES = [os.path.join(CSRC, "nb_kernels.hip"), os.path.join(CSRC, "nb_probe.hip"),
+           os.path.join(CSRC, "nb_runtime.cpp")]
 ARCH = "gfx950"
 
 HIP_FLAGS = [

@@ -168,5 +168,6 @@ hipError_t launch_l1_classify(const Launch &L, int mode, int init, hipStream_t s
 hipError_t launch_finalize_l1(const Launch &L, int init, hipStream_t s);
 hipError_t launch_diag(const Launch &L, int mode, int with_pe, hipStream_t s);
 hipError_t launch_retention(const Launch &L, int mode, hipStream_t s);
+hipError_t launch_valu_probe(int op, float *sink, int blocks, int iters, hipStream_t s);
 
 }  // namespace nbk

@@ -405,6 +405,100 @@ Launch build_table(nb_system *const *sys, int32_t n_sys, std::vector<SysDesc> &t
     return L;
 }
 
+// Segment-table entry of one system whose workspace starts at `base` (unit_begin = ounit_begin
+// = tunit_begin = 0); st and diag are set by the caller.
+void fill_desc(SysDesc &d, const nb_params *p, const nb_buffers *b, const TileCfg &cfg,
+               const Layout &lay, char *base)
+{
+    std::memset(&d, 0, sizeof d);
+    d.x = b->x;
+    d.y = b->y;
+    d.z = b->z;
+    d.vx = b->vx;
+    d.vy = b->vy;
+    d.vz = b->vz;
+    d.ax = b->ax;
+    d.ay = b->ay;
+    d.az = b->az;
+    d.side = static_cast<int8_t *>(b->side);
+    d.part = (cfg.nsplit > 1 || cfg.sym) ? base + lay.part : nullptr;
+    d.units = cfg.sym ? reinterpret_cast<int32_t *>(base + lay.units) : nullptr;
+    d.react = cfg.sym ? reinterpret_cast<float *>(base + lay.react) : nullptr;
+    d.ch = cfg.ch;
+    d.sym = cfg.sym;
+    d.xs = base + lay.xs;
+    d.ys = base + lay.ys;
+    d.zs = base + lay.zs;
+    const bool paper = p->law == NB_LAW_PAPER;
+    d.vxs = paper ? base + lay.vxs : nullptr;
+    d.vys = paper ? base + lay.vys : nullptr;
+    d.vzs = paper ? base + lay.vzs : nullptr;
+    d.law = p->law;
+    d.perm = reinterpret_cast<int32_t *>(base + lay.perm);
+    d.tbox = reinterpret_cast<float *>(base + lay.tbox);
+    d.npad = cfg.npad;
+    d.p1 = cfg.p1;
+    d.nalloc = cfg.nalloc;
+    d.ntiles = cfg.ntiles;
+    d.tunit_begin = 0;
+    d.red = reinterpret_cast<double *>(base + lay.red);
+    d.pe_part = reinterpret_cast<double *>(base + lay.pe);
+    d.l1_log = reinterpret_cast<int32_t *>(base + lay.log);
+    d.n = (int32_t)p->n;
+    d.n1 = (int32_t)p->n1;
+    d.nsplit = cfg.nsplit;
+    d.jchunk = cfg.jchunk;
+    d.iblock = cfg.iblock;
+    d.n_iblocks = cfg.n_iblocks;
+    d.n_units = cfg.n_units;
+    d.n_ounits = cfg.n_ounits;
+    d.unit_begin = 0;
+    d.ounit_begin = 0;
+    d.n_peunits = cfg.n_ounits;
+}
+
+// Initial device state of a system: FP64 masters and the derived FP32 force constants.
+void fill_state(DevState &init, const nb_params *p)
+{
+    std::memset(&init, 0, sizeof init);
+    init.D1 = p->D1;
+    init.D2 = p->D2;
+    init.D2_0 = p->D2;
+    init.R2_0 = p->R2_0;
+    init.rL_a = roche_lobe_ratio(p->q) * p->a;
+    init.growth_rate = p->growth_rate;
+    init.G = p->G;
+    init.m = p->m;
+    init.dt = p->dt;
+    init.xi_l1 = l1_from_accretor(p->q);
+    const double Ds[3] = {p->D1, 0.5 * (p->D1 + p->D2), p->D2};
+    for (int k = 0; k < 3; ++k) {
+        init.c1d[k] = 11.0 / (Ds[k] * Ds[k] * Ds[k]);
+        init.c2d[k] = 10.0 / (Ds[k] * Ds[k]);
+        init.c1f[k] = (float)init.c1d[k];
+        init.c2f[k] = (float)init.c2d[k];
+        init.far2f[k] = (float)(Ds[k] * Ds[k] * (1.0 + (double)FAR_MARGIN));
+    }
+    init.gm_d = p->G * p->m;
+    init.h_d = 0.5 * p->dt;
+    init.gm_f = (float)init.gm_d;
+    init.h_f = (float)init.h_d;
+    init.dt_f = (float)p->dt;
+    init.growth_on = p->growth_on ? 1 : 0;
+    init.law = p->law;
+    init.gamma = p->gamma;
+    init.beta = p->beta;
+    init.leps_d = p->eps;
+    if (p->law == NB_LAW_PAPER) {
+        init.lgc_d = p->gamma * PI / (12.0 * p->G * p->m * p->m);
+        init.lgcb_d = p->beta * init.lgc_d;
+    }
+    for (int k = 0; k < 3; ++k) init.lD_f[k] = (float)Ds[k];
+    init.leps_f = (float)p->eps;
+    init.lgc_f = (float)init.lgc_d;
+    init.lgcb_f = (float)init.lgcb_d;
+}
+
 }  // namespace
 
 extern "C" {
@@ -505,92 +599,12 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
     s->d_diag = reinterpret_cast<DiagOut *>(base + lay.diag);
 
     SysDesc &d = s->desc;
-    std::memset(&d, 0, sizeof d);
-    d.x = b->x;
-    d.y = b->y;
-    d.z = b->z;
-    d.vx = b->vx;
-    d.vy = b->vy;
-    d.vz = b->vz;
-    d.ax = b->ax;
-    d.ay = b->ay;
-    d.az = b->az;
-    d.side = static_cast<int8_t *>(b->side);
+    fill_desc(d, p, b, cfg, lay, base);
     d.st = s->d_state;
-    d.part = (cfg.nsplit > 1 || cfg.sym) ? base + lay.part : nullptr;
-    d.units = cfg.sym ? reinterpret_cast<int32_t *>(base + lay.units) : nullptr;
-    d.react = cfg.sym ? reinterpret_cast<float *>(base + lay.react) : nullptr;
-    d.ch = cfg.ch;
-    d.sym = cfg.sym;
-    d.xs = base + lay.xs;
-    d.ys = base + lay.ys;
-    d.zs = base + lay.zs;
-    const bool paper = p->law == NB_LAW_PAPER;
-    d.vxs = paper ? base + lay.vxs : nullptr;
-    d.vys = paper ? base + lay.vys : nullptr;
-    d.vzs = paper ? base + lay.vzs : nullptr;
-    d.law = p->law;
-    d.perm = reinterpret_cast<int32_t *>(base + lay.perm);
-    d.tbox = reinterpret_cast<float *>(base + lay.tbox);
-    d.npad = cfg.npad;
-    d.p1 = cfg.p1;
-    d.nalloc = cfg.nalloc;
-    d.ntiles = cfg.ntiles;
-    d.tunit_begin = 0;
-    d.red = reinterpret_cast<double *>(base + lay.red);
-    d.pe_part = reinterpret_cast<double *>(base + lay.pe);
-    d.l1_log = reinterpret_cast<int32_t *>(base + lay.log);
     d.diag = s->d_diag;
-    d.n = (int32_t)p->n;
-    d.n1 = (int32_t)p->n1;
-    d.nsplit = cfg.nsplit;
-    d.jchunk = cfg.jchunk;
-    d.iblock = cfg.iblock;
-    d.n_iblocks = cfg.n_iblocks;
-    d.n_units = cfg.n_units;
-    d.n_ounits = cfg.n_ounits;
-    d.unit_begin = 0;
-    d.ounit_begin = 0;
-    d.n_peunits = cfg.n_ounits;
-
     DevState init;
-    std::memset(&init, 0, sizeof init);
-    init.D1 = p->D1;
-    init.D2 = p->D2;
-    init.D2_0 = p->D2;
-    init.R2_0 = p->R2_0;
-    init.rL_a = roche_lobe_ratio(p->q) * p->a;
-    init.growth_rate = p->growth_rate;
-    init.G = p->G;
-    init.m = p->m;
-    init.dt = p->dt;
-    init.xi_l1 = l1_from_accretor(p->q);
-    const double Ds[3] = {p->D1, 0.5 * (p->D1 + p->D2), p->D2};
-    for (int k = 0; k < 3; ++k) {
-        init.c1d[k] = 11.0 / (Ds[k] * Ds[k] * Ds[k]);
-        init.c2d[k] = 10.0 / (Ds[k] * Ds[k]);
-        init.c1f[k] = (float)init.c1d[k];
-        init.c2f[k] = (float)init.c2d[k];
-        init.far2f[k] = (float)(Ds[k] * Ds[k] * (1.0 + (double)FAR_MARGIN));
-    }
-    init.gm_d = p->G * p->m;
-    init.h_d = 0.5 * p->dt;
-    init.gm_f = (float)init.gm_d;
-    init.h_f = (float)init.h_d;
-    init.dt_f = (float)p->dt;
-    init.growth_on = p->growth_on ? 1 : 0;
-    init.law = p->law;
-    init.gamma = p->gamma;
-    init.beta = p->beta;
-    init.leps_d = p->eps;
-    if (p->law == NB_LAW_PAPER) {
-        init.lgc_d = p->gamma * PI / (12.0 * p->G * p->m * p->m);
-        init.lgcb_d = p->beta * init.lgc_d;
-    }
-    for (int k = 0; k < 3; ++k) init.lD_f[k] = (float)Ds[k];
-    init.leps_f = (float)p->eps;
-    init.lgc_f = (float)init.lgc_d;
-    init.lgcb_f = (float)init.lgcb_d;
+    fill_state(init, p);
+    const bool paper = p->law == NB_LAW_PAPER;
 
     hipStream_t st = static_cast<hipStream_t>(stream);
     int rc = NB_OK;
@@ -863,6 +877,22 @@ int nb_retention(nb_system *s, int32_t *n_past, int32_t *n_bound, void *stream)
     return NB_OK;
 }
 
+int nb_nonfinite_async(nb_system *const *sys, int32_t n_sys, int32_t *out_host, void *stream)
+{
+    if (!out_host) return NB_E_INVAL;
+    // the same checks as a step over these systems: distinct, each on its own (current) device
+    if (!sys || n_sys < 1) return NB_E_INVAL;
+    for (int k = 0; k < n_sys; ++k) {
+        if (!sys[k] || !on_own_device(sys[k])) return NB_E_INVAL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (int k = 0; k < n_sys; ++k) {
+        NB_TRY(hipMemcpyAsync(out_host + k, &sys[k]->d_state->nonfinite, sizeof(int32_t),
+                              hipMemcpyDeviceToHost, st));
+    }
+    return NB_OK;
+}
+
 int nb_l1_log(nb_system *s, int32_t *out_host, int32_t max_steps, int32_t *n_out, void *stream)
 {
     if (!s || !n_out || max_steps < 0 || (max_steps > 0 && !out_host) || !on_own_device(s))
@@ -883,6 +913,37 @@ int nb_l1_log(nb_system *s, int32_t *out_host, int32_t max_steps, int32_t *n_out
         std::memcpy(out_host + 4 * r, src, 4 * sizeof(int32_t));
     }
     *n_out = (int32_t)rows;
+    return NB_OK;
+}
+
+int nb_valu_probe(int32_t op, int32_t blocks, int32_t iters, void *sink, void *stream,
+                  double *ms, int64_t *lane_ops)
+{
+    if (op < 0 || op > 3 || blocks < 1 || iters < 1 || !sink || !ms || !lane_ops)
+        return NB_E_INVAL;
+    int device = -1;
+    NB_TRY(hipGetDevice(&device));
+    if (!device_buffer(sink, device)) return NB_E_INVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess) return NB_E_HIP;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return NB_E_HIP;
+    }
+    int rc = NB_OK;
+    float t = 0.f;
+    if (hipEventRecord(a, st) != hipSuccess ||
+        launch_valu_probe(op, static_cast<float *>(sink), blocks, iters, st) != hipSuccess ||
+        hipEventRecord(b, st) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(&t, a, b) != hipSuccess)
+        rc = NB_E_HIP;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc != NB_OK) return rc;
+    *ms = t;
+    // eight chains per lane; op 3 issues three FMAs and one reciprocal square root per chain step
+    *lane_ops = (int64_t)blocks * 256 * (int64_t)iters * 8 * (op == 3 ? 4 : 1);
     return NB_OK;
 }
 

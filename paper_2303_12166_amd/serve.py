@@ -25,6 +25,12 @@ completion before the next one starts.
 
 Each system's kernels, work split and reduction orders depend on its own size only, so its result
 is bitwise the same alone and in any mix; both runs record a digest of every final state.
+
+After every round the server reads each of the round's systems' non-finite counts (positions or
+velocities that are NaN or infinite after the round's last step). A system that has one is
+evicted at once with status ``"failed"``: queued rounds are drained first (they may still hold
+it), then its graphs and device memory are released. Other systems are unaffected, since no
+kernel reads another system's state.
 """
 
 from __future__ import annotations
@@ -45,6 +51,7 @@ from . import (
     nb_graph_create,
     nb_graph_destroy,
     nb_graph_launch,
+    nb_nonfinite_async,
     nb_scratch_bytes,
 )
 from .system import System
@@ -62,6 +69,7 @@ class Record:
     bytes: int = 0
     status: str = "pending"
     digest: str = ""
+    state: tuple = ()  # (positions, velocities) of the final state, with keep_states
 
 
 def footprint_bytes(n: int, q: float, mode: str = "kahan") -> int:
@@ -105,6 +113,11 @@ def _build(req, mode: str, dt: float, stream) -> System:
     return System.from_ic(ic, mode=mode, dt=dt, stream=stream)
 
 
+def _final_state(system: System) -> tuple:
+    system.synchronize()
+    return system.positions(), system.velocities()
+
+
 def summarize(records, t0: float = 0.0) -> dict:
     done = [r for r in records if r.status == "done"]
     if not done:
@@ -115,6 +128,7 @@ def summarize(records, t0: float = 0.0) -> dict:
     return {
         "completed": len(done),
         "rejected": sum(r.status == "rejected" for r in records),
+        "failed": sum(r.status == "failed" for r in records),
         "span_s": span,
         "sims_per_s": len(done) / span if span > 0 else float("nan"),
         "interactions_per_s": inter / span if span > 0 else float("nan"),
@@ -129,7 +143,7 @@ class BatchServer:
     def __init__(self, budget_bytes: int, round_steps: int = 10, max_active: int = 512,
                  mode: str = "kahan", dt: float = 1e-4, use_graphs: bool = True,
                  keep_digests: bool = True, policy: str = "srpt", fill: float = 1.2e10,
-                 workers: int = 2, depth: int = 2):
+                 workers: int = 2, depth: int = 2, keep_states: bool = False):
         if policy not in ("srpt", "all"):
             raise ValueError("policy must be 'srpt' or 'all'")
         import torch
@@ -149,8 +163,34 @@ class BatchServer:
         self.compute = torch.cuda.Stream()
         self.copy_stream = torch.cuda.Stream()
         self.admit_stream = torch.cuda.Stream()
+        self.keep_states = keep_states
         self.rounds = 0
         self.graphs_built = 0
+        self.evicted = 0
+        # pinned host slots for the per-round non-finite counts
+        self._flags = torch.zeros(self.max_active, dtype=torch.int32, pin_memory=True)
+
+    # -------------------------------------------------------------- hooks
+
+    def build_system(self, req) -> System:
+        """Creates the system of a request on the admission stream (runs in a worker thread)."""
+        return _build(req, self.mode, self.dt, self.admit_stream)
+
+    def on_round_queued(self, systems) -> None:
+        """Called after each round is queued on the compute stream, with the round's systems
+        (a subclass may queue its own work there)."""
+
+    def _nonfinite(self, entries, ev) -> list:
+        """Entries of a completed round whose system holds a non-finite element."""
+        if not entries:
+            return []
+        if len(entries) > self._flags.numel():
+            self._flags = self.torch.zeros(len(entries), dtype=self.torch.int32, pin_memory=True)
+        self.copy_stream.wait_event(ev)
+        nb_nonfinite_async([a[0].handle for a in entries], self._flags, self.copy_stream)
+        self.copy_stream.synchronize()
+        flags = self._flags[: len(entries)].tolist()
+        return [a for a, f in zip(entries, flags) if f != 0]
 
     # -------------------------------------------------------------- admission worker
 
@@ -161,7 +201,7 @@ class BatchServer:
                 return
             req, rec = item
             try:
-                sysm = _build(req, self.mode, self.dt, self.admit_stream)
+                sysm = self.build_system(req)
                 sysm.use_on(self.compute)
                 ready.put((req, rec, sysm, None))
             except Exception as e:  # reported by the main loop
@@ -257,6 +297,7 @@ class BatchServer:
                         from . import nb_step
 
                         nb_step([a[0].handle for a in chosen], k, self.compute)
+                    self.on_round_queued([a[0] for a in chosen])
                     ev = self.torch.cuda.Event()
                     ev.record(self.compute)
                     self.rounds += 1
@@ -265,25 +306,40 @@ class BatchServer:
                         a[2] -= k
                         if a[2] <= 0:
                             finishing.append(a)
-                    inflight.append((ev, finishing, key))
+                    inflight.append((ev, finishing, key, chosen))
                     continue
                 if not inflight:
                     continue
-                # the oldest queued round: wait for it, then retire the systems it finished
-                ev, finishing, _ = inflight.popleft()
+                # the oldest queued round: wait for it, check its systems, then retire the ones
+                # it finished
+                ev, finishing, _, chosen = inflight.popleft()
                 ev.synchronize()
                 t = now()
-                if finishing:
+                failed = self._nonfinite([a for a in chosen if a[1].status != "failed"], ev)
+                if failed:
+                    # rounds queued after this one may still step them: drain the queue first
+                    self.compute.synchronize()
+                    for a in failed:
+                        a[1].status = "failed"
+                        a[1].t_done = t
+                        a[2] = 0
+                    self.evicted += len(failed)
+                finishing = [a for a in finishing if a[1].status != "failed"]
+                if finishing or failed:
                     for a in finishing:
                         sysm, rec = a[0], a[1]
                         rec.t_done = t
                         rec.status = "done"
                         if self.keep_digests:
                             rec.digest = state_digest(sysm, self.copy_stream, ev)
-                    gone = {a[1].rid for a in finishing}
+                        if self.keep_states:
+                            self.copy_stream.wait_event(ev)
+                            self.copy_stream.synchronize()
+                            rec.state = _final_state(sysm)
+                    gone = {a[1].rid for a in finishing + failed}
                     for gk in [gk for gk in graphs if gone.intersection(gk[0])]:
                         nb_graph_destroy(graphs.pop(gk))
-                    for a in finishing:
+                    for a in finishing + failed:
                         reserved -= a[1].bytes
                         a[0].close()
                     active = [a for a in active if a[1].rid not in gone]
@@ -310,8 +366,9 @@ class BatchServer:
 
 
 def run_sequential(trace, mode: str = "kahan", dt: float = 1e-4, chunk: int = 100,
-                   keep_digests: bool = True, log=None) -> list:
-    """One system at a time, in arrival order, each stepped alone to completion."""
+                   keep_digests: bool = True, log=None, keep_states: bool = False) -> list:
+    """One system at a time, in arrival order, each stepped alone to completion. A system whose
+    final state holds a non-finite element is reported ``"failed"``."""
     import torch
 
     stream = torch.cuda.Stream()
@@ -332,9 +389,11 @@ def run_sequential(trace, mode: str = "kahan", dt: float = 1e-4, chunk: int = 10
             left -= k
         sysm.synchronize()
         rec.t_done = time.perf_counter() - t0
-        rec.status = "done"
+        rec.status = "failed" if sysm.diagnostics()["nonfinite"] else "done"
         if keep_digests:
             rec.digest = state_digest(sysm)
+        if keep_states:
+            rec.state = _final_state(sysm)
         sysm.close()
         if log:
             log("seq t=%.2fs done rid=%d n=%d" % (rec.t_done, rec.rid, rec.n))

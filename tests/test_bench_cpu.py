@@ -27,3 +27,19 @@ def test_counter_record_requires_matching_source_and_split():
         assert bench.counter_record("c3", "kahan", entry["nsplit"]) == entry
     assert bench.counter_record("c3", "kahan", entry["nsplit"] + 1) is None
     assert bench.counter_record("c3", "nonexistent-mode", entry["nsplit"]) is None
+
+
+def test_served_sample_takes_one_request_per_size_decile():
+    sys.path.insert(0, ROOT)
+    import bench
+
+    trace, desc = bench.serving_trace("full")
+    assert len(trace) == 256 and "256 requests" in desc
+    sample = bench.served_sample(trace)
+    assert len(sample) == 10
+    ns = [r.n for r in sample]
+    assert ns == sorted(ns)
+    all_n = sorted(r.n for r in trace)
+    for d, r in enumerate(sample):  # each pick lies inside its own tenth of the sizes
+        assert all_n[d * 256 // 10] <= r.n <= all_n[(d + 1) * 256 // 10 - 1]
+    assert len({r.rid for r in sample}) == 10

@@ -109,3 +109,52 @@ def test_server_admission_under_small_budget():
                               round_steps=5)
     out = tight.run(big[:1])
     assert out[0].status == "rejected"
+
+
+def test_nonfinite_system_is_evicted_and_the_others_are_unchanged():
+    """A NaN written into one system's positions while its batch runs (queued on the compute
+    stream after the third round): that request ends "failed" and leaves the server early; every
+    other request still ends bit for bit as in its one-at-a-time run."""
+    require_gpu()
+    import torch
+
+    from paper_2303_12166_amd import serve
+
+    print_case("serve nonfinite eviction")
+    trace = _small_trace(count=8, steps=40, rate=2000.0, seed=13)
+    victim = trace[2].rid
+
+    class Poisoning(serve.BatchServer):
+        def __init__(self, *a, **kw):
+            super().__init__(*a, **kw)
+            self.by_handle = {}
+            self.poisoned_at = None
+
+        def build_system(self, req):
+            s = super().build_system(req)
+            self.by_handle[s.handle.value] = req.rid
+            return s
+
+        def on_round_queued(self, systems):
+            if self.poisoned_at is None and self.rounds >= 2:
+                for s in systems:
+                    if self.by_handle.get(s.handle.value) == victim:
+                        with torch.cuda.stream(self.compute):
+                            s.x[5:6].fill_(float("nan"))
+                        self.poisoned_at = self.rounds
+
+    server = Poisoning(budget_bytes=8 << 30, round_steps=5, fill=1e9)
+    recs = server.run(trace)
+    seq = serve.run_sequential(trace, chunk=9)
+    assert server.poisoned_at is not None
+    assert server.evicted == 1
+    by = {r.rid: r for r in recs}
+    assert by[victim].status == "failed"
+    assert by[victim].t_done >= by[victim].t_arrive
+    for rb, rs in zip(recs, seq):
+        if rb.rid == victim:
+            continue
+        assert rb.status == "done" and rs.status == "done"
+        assert rb.digest == rs.digest, rb.rid
+    s = serve.summarize(recs)
+    assert s["completed"] == len(trace) - 1 and s["failed"] == 1
