@@ -52,6 +52,7 @@ extern "C" {
 #define NB_E_NONFINITE (-4) /* a position or velocity became NaN or infinite */
 #define NB_E_MISMATCH (-5)  /* systems of different precision modes or element laws in one
                                multi-system call */
+#define NB_E_LIMIT (-6)     /* more systems than nb_step_static's fixed table holds */
 
 /* element laws */
 #define NB_LAW_CONTACT 0 /* conservative contact law (default; see the header comment) */
@@ -148,6 +149,21 @@ int nb_forces(nb_system *s, void *stream);
  * calls on one stream are ordered, calls on different streams do not share a table.
  * Asynchronous on `stream`. */
 int nb_step(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *stream);
+
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): nb_step with the multi-system segment table kept in a fixed array of
+ * NB_STATIC_MAX_SYS entries in each GPU's memory (76 KB, held by the library until the
+ * process ends) instead of a table the library allocates. The same work and bitwise the same
+ * results as nb_step(sys, n_sys, n_steps, stream); any n_sys from 1 to NB_STATIC_MAX_SYS.
+ * Allocates no device or host memory and synchronises nothing: the table is rewritten on the
+ * device by a small kernel queued on `stream` ahead of the steps, from each system's own
+ * one-entry table. Every call on a GPU shares that GPU's one table, which keeps the last call's
+ * contents: calls that overlap on one GPU (on different streams, or from different threads
+ * without ordering) race, so order them on one stream. Force-kernel timing (nb_timing_*) does
+ * not cover these calls. n_sys > NB_STATIC_MAX_SYS returns NB_E_LIMIT and queues nothing; the
+ * other errors are nb_step's. */
+#define NB_STATIC_MAX_SYS 256
+int nb_step_static(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *stream);
 
 /* Captures n_steps steps of the listed systems (exactly the work nb_step would queue for them)
  * into a HIP graph with its own copy of the segment table, for replay with nb_graph_launch. The

@@ -23,6 +23,7 @@ from ._abi import (  # noqa: F401
     NB_LAW_PAPER,
     NB_E_HIP,
     NB_E_INVAL,
+    NB_E_LIMIT,
     NB_E_MISMATCH,
     NB_E_NOMEM,
     NB_E_NONFINITE,
@@ -31,6 +32,7 @@ from ._abi import (  # noqa: F401
     NB_FP64,
     NB_L1_LOG_CAP,
     NB_OK,
+    NB_STATIC_MAX_SYS,
     NbBuffers,
     NbDiag,
     NbParams,
@@ -125,6 +127,15 @@ def nb_step(handles, n_steps: int, stream=None) -> None:
     arr = (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h
                                              for h in handles])
     _check(load().nb_step(arr, len(handles), int(n_steps), _stream(stream)), "nb_step")
+
+
+def nb_step_static(handles, n_steps: int, stream=None) -> None:
+    """nb_step with the segment table in the library's fixed per-GPU array (no allocation);
+    at most NB_STATIC_MAX_SYS systems, and calls on one GPU must be ordered on one stream."""
+    arr = (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h
+                                             for h in handles])
+    _check(load().nb_step_static(arr, len(handles), int(n_steps), _stream(stream)),
+           "nb_step_static")
 
 
 def nb_diagnostics(handle: ctypes.c_void_p, with_pe: bool = False, stream=None) -> dict:

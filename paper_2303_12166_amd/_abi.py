@@ -14,6 +14,8 @@ NB_E_HIP = -2
 NB_E_NOMEM = -3
 NB_E_NONFINITE = -4
 NB_E_MISMATCH = -5
+NB_E_LIMIT = -6
+NB_STATIC_MAX_SYS = 256
 
 NB_FP32_PLAIN = 0
 NB_FP32_KAHAN = 1
@@ -30,6 +32,7 @@ EXPORTED = (
     "nb_create",
     "nb_forces",
     "nb_step",
+    "nb_step_static",
     "nb_diagnostics",
     "nb_l1_log",
     "nb_nonfinite_async",
@@ -111,6 +114,7 @@ def declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.nb_create.argtypes = [P(NbParams), P(NbBuffers), _vp, P(_vp)]
     lib.nb_forces.argtypes = [_vp, _vp]
     lib.nb_step.argtypes = [P(_vp), _i32, _i32, _vp]
+    lib.nb_step_static.argtypes = [P(_vp), _i32, _i32, _vp]
     lib.nb_diagnostics.argtypes = [_vp, _i32, P(NbDiag), _vp]
     lib.nb_l1_log.argtypes = [_vp, P(_i32), _i32, P(_i32), _vp]
     lib.nb_nonfinite_async.argtypes = [P(_vp), _i32, P(_i32), _vp]

@@ -154,6 +154,16 @@ struct Launch {
     int32_t law;           // element law of every system in the launch (NB_LAW_*)
 };
 
+// Segment-table entries written on the device from the systems' own one-entry tables (each
+// system's SysDesc in its workspace), with this launch's prefix offsets: up to TABLE_CHUNK
+// systems per kernel launch, passed by value as a kernel argument.
+constexpr int TABLE_CHUNK = 64;
+struct TableChunk {
+    const SysDesc *src[TABLE_CHUNK];
+    int32_t unit_begin[TABLE_CHUNK], ounit_begin[TABLE_CHUNK], tunit_begin[TABLE_CHUNK];
+    int32_t first, count;  // entries [first, first + count) of the destination table
+};
+
 // Host-side launchers (nb_kernels.hip). All return the HIP status of the launch.
 hipError_t launch_init_state(DevState *st, const DevState &init, hipStream_t s);
 hipError_t launch_fill_sorted(void *xs, void *ys, void *zs, int nalloc, int mode, bool sentinel,
@@ -169,5 +179,6 @@ hipError_t launch_finalize_l1(const Launch &L, int init, hipStream_t s);
 hipError_t launch_diag(const Launch &L, int mode, int with_pe, hipStream_t s);
 hipError_t launch_retention(const Launch &L, int mode, hipStream_t s);
 hipError_t launch_valu_probe(int op, float *sink, int blocks, int iters, hipStream_t s);
+hipError_t launch_copy_table(SysDesc *dst, const TableChunk &c, hipStream_t s);
 
 }  // namespace nbk

@@ -1636,11 +1636,39 @@ __global__ __launch_bounds__(BT) void k_ret_total(Launch L)
     }
 }
 
+// Copies entry k of the chunk: the system's own SysDesc word by word, with the launch's prefix
+// offsets in place of its zero ones. One block per entry.
+__global__ __launch_bounds__(64) void k_copy_table(SysDesc *dst, TableChunk c)
+{
+    static_assert(sizeof(SysDesc) % 4 == 0, "SysDesc is copied in 32-bit words");
+    constexpr int W = (int)(sizeof(SysDesc) / 4);
+    constexpr int WU = (int)(offsetof(SysDesc, unit_begin) / 4);
+    constexpr int WO = (int)(offsetof(SysDesc, ounit_begin) / 4);
+    constexpr int WT = (int)(offsetof(SysDesc, tunit_begin) / 4);
+    const int k = blockIdx.x;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(c.src[k]);
+    uint32_t *out = reinterpret_cast<uint32_t *>(dst + c.first + k);
+    for (int w = threadIdx.x; w < W; w += blockDim.x) {
+        uint32_t v = src[w];
+        if (w == WU) v = (uint32_t)c.unit_begin[k];
+        if (w == WO) v = (uint32_t)c.ounit_begin[k];
+        if (w == WT) v = (uint32_t)c.tunit_begin[k];
+        out[w] = v;
+    }
+}
+
 // ------------------------------------------------------------------ launchers
 
 static inline int grid_for(int units)
 {
     return units < 1 ? 1 : units;
+}
+
+hipError_t launch_copy_table(SysDesc *dst, const TableChunk &c, hipStream_t s)
+{
+    if (c.count < 1 || c.count > TABLE_CHUNK) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_copy_table, dim3(c.count), dim3(64), 0, s, dst, c);
+    return hipGetLastError();
 }
 
 hipError_t launch_init_state(DevState *st, const DevState &init, hipStream_t s)

@@ -250,6 +250,36 @@ std::atomic<int> g_force_grid{0};
 
 }  // namespace
 
+// Segment table of nb_step_static: a fixed array in each GPU's memory, held until the process
+// ends. In host code `scratch` only names the symbol; its device address on each GPU comes from
+// hipGetSymbolAddress (static_table below), taken once per device with that device current.
+static __device__ __align__(256) SysDesc scratch[NB_STATIC_MAX_SYS];
+
+namespace {
+
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex g_static_mu;
+SysDesc *g_static_ptr[STATIC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device `device` (looked up on first use).
+int static_table(int device, SysDesc **out)
+{
+    if (device < 0 || device >= STATIC_MAX_DEVICES) return NB_E_INVAL;
+    std::lock_guard<std::mutex> g(g_static_mu);
+    if (!g_static_ptr[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return NB_E_HIP;
+        }
+        g_static_ptr[device] = static_cast<SysDesc *>(ptr);
+    }
+    *out = g_static_ptr[device];
+    return NB_OK;
+}
+
+}  // namespace
+
 struct nb_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -514,6 +544,7 @@ const char *nb_strerror(int status)
     case NB_E_NOMEM: return "workspace too small, table allocation failed or system too large";
     case NB_E_NONFINITE: return "non-finite position or velocity";
     case NB_E_MISMATCH: return "systems of different modes or element laws in one call";
+    case NB_E_LIMIT: return "more systems than the static segment table holds (NB_STATIC_MAX_SYS)";
     default: return "unknown status";
     }
 }
@@ -756,6 +787,46 @@ int nb_step(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *stream)
     }
     L.sys = bt->d;
     return run_steps(L, mode, n_steps, combine, st);
+}
+
+int nb_step_static(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *stream)
+{
+    if (n_steps < 0) return NB_E_INVAL;
+    if (sys && n_sys > NB_STATIC_MAX_SYS) return NB_E_LIMIT;
+    const int chk = check_system_list(sys, n_sys);
+    if (chk != NB_OK) return chk;
+    int device = -1;
+    NB_TRY(hipGetDevice(&device));
+    SysDesc *table = nullptr;
+    const int rc = static_table(device, &table);
+    if (rc != NB_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // the table is rewritten on the device, ordered on `stream` before the steps that read it:
+    // each entry is the system's own one-entry table with this call's prefix offsets
+    Launch L{};
+    L.n_sys = n_sys;
+    L.law = sys[0]->p.law;
+    bool combine = false;
+    TableChunk c;
+    for (int first = 0; first < n_sys; first += TABLE_CHUNK) {
+        std::memset(&c, 0, sizeof c);
+        c.first = first;
+        c.count = std::min(TABLE_CHUNK, n_sys - first);
+        for (int k = 0; k < c.count; ++k) {
+            const nb_system *s = sys[first + k];
+            c.src[k] = s->d_desc;
+            c.unit_begin[k] = L.total_units;
+            c.ounit_begin[k] = L.total_ounits;
+            c.tunit_begin[k] = L.total_tunits;
+            L.total_units += s->cfg.n_units;
+            L.total_ounits += s->cfg.n_ounits;
+            L.total_tunits += s->cfg.ntiles;
+            combine = combine || s->cfg.nsplit > 1 || s->cfg.sym;
+        }
+        NB_TRY(launch_copy_table(table, c, st));
+    }
+    L.sys = table;
+    return run_steps(L, sys[0]->p.mode, n_steps, combine, st, false);
 }
 
 int nb_graph_create(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *stream,

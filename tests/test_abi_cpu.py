@@ -132,6 +132,19 @@ def test_step_rejects_bad_arguments(nb):
     assert lib.nb_step(arr, 0, 1, None) == nb.NB_E_INVAL
 
 
+def test_step_static_rejects_bad_arguments(nb):
+    lib = nb.load()
+    assert lib.nb_step_static(None, 1, 1, None) == nb.NB_E_INVAL
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.nb_step_static(arr, 1, 1, None) == nb.NB_E_INVAL
+    assert lib.nb_step_static(arr, 0, 1, None) == nb.NB_E_INVAL
+    assert lib.nb_step_static(arr, 1, -1, None) == nb.NB_E_INVAL
+    # more systems than the fixed table holds: refused before any entry is looked at
+    many = (ctypes.c_void_p * (nb.NB_STATIC_MAX_SYS + 1))()
+    assert lib.nb_step_static(many, nb.NB_STATIC_MAX_SYS + 1, 1, None) == nb.NB_E_LIMIT
+    assert "static segment table" in nb.nb_strerror(nb.NB_E_LIMIT)
+
+
 def test_strerror_and_version(nb):
     assert nb.nb_strerror(nb.NB_E_NOMEM).startswith("workspace")
     assert nb.nb_strerror(12345) == "unknown status"
