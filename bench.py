@@ -52,9 +52,9 @@ WORKLOADS = {
     "c4": dict(n=131072, q=0.8, mode="kahan", steps=200, warmup=5),
 }
 
-KERNEL_NAMES = {"kahan": "k_force_sym", "plain": "k_force_f32<1,false>",
-                "fp64": "k_force_sym64<0>"}
-PAPER_KERNEL_NAMES = {"kahan": "k_force_sym_paper", "fp64": "k_force_sym64<1>"}
+# force kernel of each mode; the FP32 Kahan kernels are instantiated per band height (%d)
+KERNEL_NAMES = {"kahan": "k_force_sym<%d>", "plain": "k_force_f32", "fp64": "k_force_sym64<0>"}
+PAPER_KERNEL_NAMES = {"kahan": "k_force_sym_paper<%d>", "fp64": "k_force_sym64<1>"}
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "force_counters.json")
 # the sources that decide the kernels' machine code: the kernels and their compile-time knobs
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2303_12166_amd", "csrc", f)
@@ -73,7 +73,7 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def counter_record(workload: str, mode: str, nsplit: int):
+def counter_record(workload: str, mode: str, cfg: dict):
     """The committed rocprofv3 counter record of this workload's force kernel, if it was taken
     with this kernel source and work split (HBM bytes per launch, VALU instructions per pair)."""
     try:
@@ -84,7 +84,7 @@ def counter_record(workload: str, mode: str, nsplit: int):
     entry = rec.get("%s:%s" % (workload, mode))
     if not entry or entry.get("kernel_sha") != kernel_source_sha():
         return None
-    if entry.get("nsplit") != nsplit:
+    if entry.get("nsplit") != cfg["nsplit"] or entry.get("rows", 1) != cfg["rows"]:
         return None
     return entry
 
@@ -190,7 +190,9 @@ def valu_probe() -> dict:
     blocks = N_CU * 4 * 8 // 4
     out = {}
     for op, name, iters in ((0, "v_fma_f32", 65536), (1, "v_rsq_f32", 16384),
-                            (2, "v_rcp_f32", 16384), (3, "3 v_fma_f32 + 1 v_rsq_f32", 16384)):
+                            (2, "v_rcp_f32", 16384), (3, "3 v_fma_f32 + 1 v_rsq_f32", 16384),
+                            (4, "v_fmac_f32", 65536), (5, "v_add_f32", 65536),
+                            (6, "v_mul_f32", 65536), (7, "v_sub_f32 (DPP wave_ror:1 source)", 65536)):
         nb.nb_valu_probe(op, blocks, 64, sink)
         best = None
         for _ in range(3):
@@ -530,7 +532,7 @@ def main() -> int:
         law = synth.paper_law_params(ic)
     s = nb.System.from_ic(ic, mode=mode, dt=1e-4, **(law or {}))
     a0 = s.accelerations()
-    cfg = nb.nb_tile_config(n, ic.n1, nb.MODES[mode])
+    cfg = nb.nb_tile_config(n, ic.n1, nb.MODES[mode], nb.LAWS[args.law])
     log("tile config", cfg)
 
     s.step(warmup)
@@ -554,9 +556,11 @@ def main() -> int:
     value = inter * steps / elapsed
     avg_s = force_ms / max(launches, 1) / 1e3
     peak = PEAK_FP64_TFLOPS if mode == "fp64" else PEAK_FP32_TFLOPS
-    counters = counter_record(args.workload + (":paper" if law else ""), mode, cfg["nsplit"])
+    counters = counter_record(args.workload + (":paper" if law else ""), mode, cfg)
     achieved = FLOPS_PER_INTERACTION * inter / avg_s / 1e12 if avg_s > 0 else 0.0
     kernel = (PAPER_KERNEL_NAMES if law else KERNEL_NAMES)[mode]
+    if "%d" in kernel:
+        kernel = kernel % cfg["rows"]
     # pairs the kernel evaluates: N^2 / 2 with the symmetric kernels (each unordered pair once),
     # N^2 one-sided
     evaluated = inter / 2 if kernel.startswith("k_force_sym") else inter

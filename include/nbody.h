@@ -219,18 +219,25 @@ int nb_timing_enable(int32_t on);
 int nb_timing_read(double *total_ms, int64_t *launches);
 int nb_timing_reset(void);
 
-/* Work split chosen for a system of n elements (n1 in star 1) in a mode: i elements per lane
+/* Work split chosen for a system of n elements (n1 in star 1) in a mode and element law: i
+ * elements per lane
  * (ki), j chunks per i-block (nsplit; for the symmetric kernels of the FP32 Kahan and FP64 modes,
- * the chunk count of the longest tile row), i-block size and chunk length (in sorted slots). The
- * force kernels work on a copy of the positions sorted per star (Morton order of the initial
- * positions, each star padded to a multiple of 256 slots); results are returned in element
- * order. Depends only on (n, n1, mode) and the overrides below. Any output pointer may be NULL. */
-int nb_tile_config(int64_t n, int64_t n1, int32_t mode, int32_t *ki, int32_t *nsplit,
-                   int32_t *iblock, int32_t *jchunk);
+ * the chunk count of the longest band), i-block size, chunk length (in sorted slots) and band
+ * height (rows: tile rows of 256 slots whose pairs one work unit evaluates together, 1, 2 or 4
+ * in the FP32 Kahan mode, 1 otherwise; a band of k rows stores 1/k of the reaction partials of
+ * single rows). The force kernels work on a copy of the positions sorted per star (Morton order
+ * of the initial positions, each star padded to a multiple of 256 slots); results are returned
+ * in element order. Depends only on (n, n1, mode, law) and the overrides below. Any output
+ * pointer may be NULL. NB_E_INVAL for a bad size, mode or law. */
+int nb_tile_config(int64_t n, int64_t n1, int32_t mode, int32_t law, int32_t *ki, int32_t *nsplit,
+                   int32_t *iblock, int32_t *jchunk, int32_t *rows);
 
-/* Overrides the split choice for systems created afterwards whose n lies in [n_lo, n_hi]
- * (nsplit = 0 restores the built-in rule). Used by the autotuner. */
-int nb_tile_override(int64_t n_lo, int64_t n_hi, int32_t nsplit);
+/* Overrides the split choice of one (mode, law) for systems created afterwards whose n lies in
+ * [n_lo, n_hi]: nsplit chunks of the longest band and bands of `rows` tile rows (1, 2 or 4; not 1
+ * only in NB_FP32_KAHAN). nsplit = 0 restores the built-in rule (one row per band). Used by the
+ * autotuner. NB_E_INVAL for a bad mode, law, range, split or height. */
+int nb_tile_override(int64_t n_lo, int64_t n_hi, int32_t mode, int32_t law, int32_t nsplit,
+                     int32_t rows);
 
 /* Launch shape of the force kernel for calls issued afterwards (graphs keep the shape they were
  * captured with): 0 (default) launches one workgroup per work unit and lets the hardware
@@ -241,8 +248,10 @@ int nb_set_force_grid(int32_t blocks);
 
 /* Measurement aid for the force kernels' roofline (no part of the model): times one launch of an
  * issue-rate probe of the vector ALU on the current device and stream. Each of blocks x 256 lanes
- * runs iters steps of eight independent dependency chains of one instruction: op 0 v_fma_f32,
- * op 1 v_rsq_f32, op 2 v_rcp_f32, op 3 three v_fma_f32 per v_rsq_f32. *lane_ops receives the
+ * runs iters steps of eight independent dependency chains of one instruction: op 0 v_fma_f32
+ * (VOP3), op 1 v_rsq_f32, op 2 v_rcp_f32, op 3 three v_fma_f32 per v_rsq_f32, op 4 v_fmac_f32,
+ * op 5 v_add_f32, op 6 v_mul_f32 (VOP2), op 7 v_sub_f32 with a DPP wave-rotation source.
+ * *lane_ops receives the
  * lane-instructions executed, *ms the kernel time (HIP events; synchronises `stream`). `sink` is
  * a device buffer of at least 4 bytes that the probe may write (it keeps the chains live).
  * NB_E_INVAL for a bad op, size or buffer. */
@@ -251,7 +260,8 @@ int nb_valu_probe(int32_t op, int32_t blocks, int32_t iters, void *sink, void *s
 
 void nb_destroy(nb_system *s);
 const char *nb_strerror(int status);
-/* ABI version: 3 (element laws in nb_params, nb_retention). */
+/* ABI version: 4 (band height in nb_tile_config and nb_tile_override, overrides per mode and
+ * law). */
 int nb_version(void);
 
 #ifdef __cplusplus

@@ -211,15 +211,17 @@ def nb_timing_reset() -> None:
     _check(load().nb_timing_reset(), "nb_timing_reset")
 
 
-def nb_tile_config(n: int, n1: int, mode: int) -> dict:
-    v = [ctypes.c_int32(0) for _ in range(4)]
-    _check(load().nb_tile_config(int(n), int(n1), int(mode), *[ctypes.byref(x) for x in v]),
-           "nb_tile_config")
-    return dict(zip(("ki", "nsplit", "iblock", "jchunk"), (int(x.value) for x in v)))
+def nb_tile_config(n: int, n1: int, mode: int, law: int = NB_LAW_CONTACT) -> dict:
+    v = [ctypes.c_int32(0) for _ in range(5)]
+    _check(load().nb_tile_config(int(n), int(n1), int(mode), int(law),
+                                 *[ctypes.byref(x) for x in v]), "nb_tile_config")
+    return dict(zip(("ki", "nsplit", "iblock", "jchunk", "rows"), (int(x.value) for x in v)))
 
 
-def nb_tile_override(n_lo: int, n_hi: int, nsplit: int) -> None:
-    _check(load().nb_tile_override(int(n_lo), int(n_hi), int(nsplit)), "nb_tile_override")
+def nb_tile_override(n_lo: int, n_hi: int, mode: int, nsplit: int, rows: int = 1,
+                     law: int = NB_LAW_CONTACT) -> None:
+    _check(load().nb_tile_override(int(n_lo), int(n_hi), int(mode), int(law), int(nsplit),
+                                   int(rows)), "nb_tile_override")
 
 
 def nb_graph_create(handles, n_steps: int, stream=None) -> ctypes.c_void_p:

@@ -122,8 +122,9 @@ def declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.nb_timing_enable.argtypes = [_i32]
     lib.nb_timing_read.argtypes = [P(ctypes.c_double), P(_i64)]
     lib.nb_timing_reset.argtypes = []
-    lib.nb_tile_config.argtypes = [_i64, _i64, _i32, P(_i32), P(_i32), P(_i32), P(_i32)]
-    lib.nb_tile_override.argtypes = [_i64, _i64, _i32]
+    lib.nb_tile_config.argtypes = [_i64, _i64, _i32, _i32, P(_i32), P(_i32), P(_i32), P(_i32),
+                                   P(_i32)]
+    lib.nb_tile_override.argtypes = [_i64, _i64, _i32, _i32, _i32, _i32]
     lib.nb_set_force_grid.argtypes = [_i32]
     lib.nb_valu_probe.argtypes = [_i32, _i32, _i32, _vp, _vp, P(ctypes.c_double), P(_i64)]
     lib.nb_graph_create.argtypes = [P(_vp), _i32, _i32, _vp, P(_vp)]

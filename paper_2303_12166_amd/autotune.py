@@ -1,14 +1,18 @@
 """Autotuner for the force kernels' work split.
 
 The kernels' compile-time shapes (tile sizes, waves per SIMD) were fixed by measurement. What
-depends on the system size is how many j chunks the work is split into: more chunks mean more,
-shorter work units (better balance across the 256 CUs, more partial sums to combine). For each
-size bucket the tuner times one whole force evaluation (gather, force kernel and combine) for
-every candidate split on a seeded two-star system and keeps the fastest; ``apply`` installs the
-table through ``nb_tile_override``, so the choice stays a function of the system size alone (a
-system gets the same split alone and in a batch).
+depends on the system size is how the pair work is cut into work units: the number of j chunks
+(more chunks mean more, shorter units: better balance across the 256 CUs, more partial sums to
+combine) and, in the FP32 Kahan mode, the band height (tile rows whose pairs one unit evaluates
+together: taller bands store fewer reaction partials and stage each j tile once for more rows,
+at fewer waves per SIMD). For each precision mode, element law and size bucket the tuner times
+one whole force evaluation (gather, force kernel and combine) for every candidate (rows, chunks)
+on a seeded two-star system and keeps the fastest; ``apply`` installs the table through
+``nb_tile_override``, so the choice stays a function of the mode, law and system size alone (a
+system gets the same split alone and in a batch). A workspace budget can exclude candidates whose
+``nb_scratch_bytes`` exceeds it.
 
-    python -m paper_2303_12166_amd.autotune [--out FILE]     # on a GPU
+    python -m paper_2303_12166_amd.autotune [--out FILE] [--keys kahan,kahan:paper,fp64]  # GPU
 """
 
 from __future__ import annotations
@@ -19,14 +23,23 @@ import math
 import os
 import sys
 
-from . import MODES, nb_tile_config, nb_tile_override, nb_version
+from . import (LAWS, MODES, NbParams, nb_scratch_bytes, nb_tile_config, nb_tile_override,
+               nb_version)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE_PATH = os.path.join(HERE, "tuning", "gfx950.json")
 
 # bucket edges (inclusive ranges) covering 4096 .. 524288 elements, factor 2 apart
 EDGES = [4096, 8192, 16384, 32768, 65536, 131072, 262144, 524288]
-CANDIDATES = (1, 2, 4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256)
+CHUNKS = (1, 2, 4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256)
+ROWS = {"kahan": (1, 2, 4), "fp64": (1,)}
+# table keys: "<mode>" for the contact law, "<mode>:paper" for eqs. (4)-(6)
+KEYS = ("kahan", "kahan:paper", "fp64", "fp64:paper")
+
+
+def split_key(key: str):
+    mode, _, law = key.partition(":")
+    return mode, law or "contact"
 
 
 def buckets():
@@ -37,14 +50,22 @@ def buckets():
     return out
 
 
+def _entries(table: dict):
+    for key, sub in table.get("tables", {}).items():
+        mode, law = split_key(key)
+        for e in sub.get("buckets", []):
+            yield MODES[mode], LAWS[law], e
+
+
 def apply(table: dict) -> None:
-    for e in table.get("buckets", []):
-        nb_tile_override(int(e["n_lo"]), int(e["n_hi"]), int(e["nsplit"]))
+    for mode, law, e in _entries(table):
+        nb_tile_override(int(e["n_lo"]), int(e["n_hi"]), mode, int(e["nsplit"]),
+                         int(e.get("rows", 1)), law=law)
 
 
 def clear(table: dict) -> None:
-    for e in table.get("buckets", []):
-        nb_tile_override(int(e["n_lo"]), int(e["n_hi"]), 0)
+    for mode, law, e in _entries(table):
+        nb_tile_override(int(e["n_lo"]), int(e["n_hi"]), mode, 0, 1, law=law)
 
 
 def load_table(path: str = TABLE_PATH):
@@ -64,14 +85,14 @@ def apply_saved(path: str = TABLE_PATH) -> bool:
     return True
 
 
-def _time_forces(ic, mode: str, repeats: int) -> float:
+def _time_forces(ic, mode: str, law_kw: dict, repeats: int) -> float:
     """Mean time of one whole force evaluation (gather, force kernel and combine), from events
     on the system's stream."""
     import torch
 
     from .system import System
 
-    s = System.from_ic(ic, mode=mode)
+    s = System.from_ic(ic, mode=mode, **law_kw)
     s.forces()
     s.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -85,56 +106,90 @@ def _time_forces(ic, mode: str, repeats: int) -> float:
     return ms / max(repeats, 1)
 
 
-def tune(mode: str = "kahan", q: float = 0.5, repeats: int = 4, max_n: int = 262144,
-         log=print) -> dict:
-    import torch
+def _workspace(ic, mode: str, law_kw: dict) -> int:
+    p = NbParams(n=ic.n, n1=ic.n1, G=ic.G, m=ic.m, dt=1e-4, D1=ic.D1, D2=ic.D2, q=ic.q, a=ic.a,
+                 R2_0=ic.R2, growth_rate=1e-4, growth_on=1, mode=MODES[mode],
+                 law=LAWS[law_kw.get("law", "contact")], pad=0, eps=law_kw.get("eps", 0.0),
+                 gamma=law_kw.get("gamma", 0.0), beta=law_kw.get("beta", 1.0))
+    return nb_scratch_bytes(p)
 
+
+def tune_key(key: str, q: float = 0.5, repeats: int = 4, max_n: int = 262144,
+             budget: int = 0, log=print) -> dict:
     import synth
 
-    table = {"arch": torch.cuda.get_device_properties(0).gcnArchName.split(":")[0],
-             "library_version": nb_version(), "mode": mode, "q": q, "buckets": []}
+    mode, law = split_key(key)
+    M, W = MODES[mode], LAWS[law]
+    out = {"q": q, "budget_bytes": budget, "buckets": []}
     for lo, hi in buckets():
         n = int(64 * round(math.sqrt(max(lo, EDGES[0] // 2) * min(hi, max_n)) / 64))
         if lo > max_n:
             break
         ic = synth.make_binary(n, q, seed=7)
+        law_kw = {}
+        if law == "paper":
+            ic = synth.with_velocity_noise(ic, 0.05, 7)
+            law_kw = synth.paper_law_params(ic)
         timings, seen = {}, set()
-        for ns in CANDIDATES:
-            nb_tile_override(n, n, ns)
-            try:
-                cfg = nb_tile_config(n, ic.n1, MODES[mode])
-                # requests that give the same work split as an earlier one are skipped
-                split = (cfg["nsplit"], cfg["jchunk"])
-                if split in seen or cfg["nsplit"] > ns:
-                    continue
-                seen.add(split)
-                timings[ns] = _time_forces(ic, mode, repeats)
-            finally:
-                nb_tile_override(n, n, 0)
+        for rows in ROWS[mode]:
+            for ns in CHUNKS:
+                nb_tile_override(n, n, M, ns, rows, law=W)
+                try:
+                    cfg = nb_tile_config(n, ic.n1, M, W)
+                    # requests that give the same work split as an earlier one are skipped
+                    split = (cfg["rows"], cfg["nsplit"], cfg["jchunk"])
+                    if split in seen or cfg["nsplit"] > ns:
+                        continue
+                    seen.add(split)
+                    if budget and _workspace(ic, mode, law_kw) > budget:
+                        continue
+                    timings["%d:%d" % (rows, ns)] = _time_forces(ic, mode, law_kw, repeats)
+                finally:
+                    nb_tile_override(n, n, M, 0, 1, law=W)
         best = min(timings, key=timings.get)
-        log("bucket [%d, %d] tuned at n=%d: nsplit %d (%.3f ms); %s" % (
-            lo, hi, n, best, timings[best],
-            " ".join("%d:%.3f" % (k, v) for k, v in sorted(timings.items()))))
-        table["buckets"].append({"n_lo": lo, "n_hi": hi, "n_tuned": n, "nsplit": best,
-                                 "ms": round(timings[best], 4),
-                                 "candidates_ms": {str(k): round(v, 4) for k, v in timings.items()}})
+        rows, ns = (int(v) for v in best.split(":"))
+        log("%s bucket [%d, %d] tuned at n=%d: rows %d nsplit %d (%.3f ms); %s" % (
+            key, lo, hi, n, rows, ns, timings[best],
+            " ".join("%s=%.3f" % (k, v) for k, v in sorted(timings.items()))))
+        out["buckets"].append({"n_lo": lo, "n_hi": hi, "n_tuned": n, "rows": rows, "nsplit": ns,
+                               "ms": round(timings[best], 4),
+                               "candidates_ms": {k: round(v, 4) for k, v in timings.items()}})
+    return out
+
+
+def tune(keys=KEYS, q: float = 0.5, repeats: int = 4, max_n: int = 262144,
+         budget: int = 0, log=print) -> dict:
+    import torch
+
+    table = {"arch": torch.cuda.get_device_properties(0).gcnArchName.split(":")[0],
+             "library_version": nb_version(), "tables": {}}
+    for key in keys:
+        table["tables"][key] = tune_key(key, q, repeats, max_n, budget, log)
     return table
 
 
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--out", default=TABLE_PATH)
-    ap.add_argument("--mode", default="kahan", choices=["kahan", "plain", "fp64"])
+    ap.add_argument("--keys", default=",".join(KEYS))
     ap.add_argument("--repeats", type=int, default=4)
     ap.add_argument("--max-n", type=int, default=262144)
+    ap.add_argument("--budget-gb", type=float, default=0.0,
+                    help="skip splits whose workspace exceeds this many GB (0: no limit)")
     args = ap.parse_args()
-    table = tune(args.mode, repeats=args.repeats, max_n=args.max_n,
+    keys = [k for k in args.keys.split(",") if k]
+    for k in keys:
+        mode, law = split_key(k)
+        if mode not in ROWS or law not in LAWS:
+            ap.error("no tunable split for %r" % k)
+    table = tune(keys, repeats=args.repeats, max_n=args.max_n,
+                 budget=int(args.budget_gb * 1e9),
                  log=lambda *a: print(*a, file=sys.stderr, flush=True))
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     with open(args.out, "w") as f:
         json.dump(table, f, indent=1)
         f.write("\n")
-    print(json.dumps({"written": args.out, "buckets": len(table["buckets"])}))
+    print(json.dumps({"written": args.out, "keys": keys}))
     return 0
 
 

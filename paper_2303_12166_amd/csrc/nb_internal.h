@@ -7,62 +7,17 @@
 
 namespace nbk {
 
-// Compile-time tuning knobs of the FP32 force kernel (defaults are the shipped configuration).
-#ifndef NB_KI32
-#define NB_KI32 1          // i elements per lane
-#endif
-#ifndef NB_JUNROLL
-#define NB_JUNROLL 2       // groups of four j per unrolled inner-loop body
-#endif
-#ifndef NB_WAVES_PER_EU
-#define NB_WAVES_PER_EU 8  // > 0: ask the compiler for this many waves per SIMD (VGPR cap)
-#endif
-#ifndef NB_SYM_UNROLL
-#define NB_SYM_UNROLL 1    // groups of four j per unrolled step of the symmetric kernel
-#endif
-#ifndef NB_SYM_DUP
-#define NB_SYM_DUP 0       // 1: each 64-element LDS group stored twice (no wrap on rotation)
-#endif
-#ifndef NB_COMBINE_SEGS
-#define NB_COMBINE_SEGS 1  // threads per element in the symmetric combine (1, 2 or 4)
-#endif
-#ifndef NB_SYM_ROWS
-#define NB_SYM_ROWS 1      // tile rows per block of the symmetric kernel (1 or 2)
-#endif
-#ifndef NB_SYM_WAVES_PER_EU
-#define NB_SYM_WAVES_PER_EU 6
-#endif
-#ifndef NB_SYM_PAPER_WAVES_PER_EU
-#define NB_SYM_PAPER_WAVES_PER_EU 6  // eqs. (4)-(6) variant: a few per-tile values spill, none
-                                     // inside the pair loop; faster than 5 waves without spills
-#endif
-#if NB_WAVES_PER_EU > 0
-#define NB_FORCE_ATTR __attribute__((amdgpu_waves_per_eu(NB_WAVES_PER_EU)))
-#else
-#define NB_FORCE_ATTR
-#endif
-#if NB_SYM_WAVES_PER_EU > 0
-#define NB_SYM_ATTR __attribute__((amdgpu_waves_per_eu(NB_SYM_WAVES_PER_EU)))
-#else
-#define NB_SYM_ATTR
-#endif
-#if NB_SYM_PAPER_WAVES_PER_EU > 0
-#define NB_SYM_PAPER_ATTR __attribute__((amdgpu_waves_per_eu(NB_SYM_PAPER_WAVES_PER_EU)))
-#else
-#define NB_SYM_PAPER_ATTR
-#endif
+// Waves per SIMD asked of the compiler (its vector-register cap) for the force kernels, by kernel
+// and band height (1, 2, 4 tile rows per lane): measured choices.
+constexpr int PLAIN_WAVES = 8;
+constexpr int SYM_WAVES[3] = {6, 5, 4};
+constexpr int SYM_PAPER_WAVES[3] = {6, 5, 4};  // eqs. (4)-(6): at one row a few per-tile values
+                                               // spill, none inside the pair loop; faster than 5
+                                               // waves without spills
 
 constexpr int BT = 256;          // threads per block, every kernel
 constexpr int TJ = 256;          // j elements staged in LDS per tile (one per thread)
-constexpr int KI32 = NB_KI32;    // i elements per lane, FP32 force kernel
-constexpr int KI64 = 1;          // i elements per lane, FP64 force kernel
-constexpr int SYM_ROWS = NB_SYM_ROWS;  // tile rows per block of the symmetric kernel
-// The FP64 mode uses the symmetric scheme too (k_force_sym64), with one tile row per block; a
-// build with two rows per block keeps the one-sided FP64 kernel.
-#ifndef NB_FP64_SYM
-#define NB_FP64_SYM 1
-#endif
-constexpr bool FP64_SYM = NB_FP64_SYM != 0 && SYM_ROWS == 1;
+constexpr int MAX_BAND = 4;      // tallest band of the FP32 symmetric kernel (tile rows per lane)
 constexpr int RED_STRIDE = 32;   // doubles per O(N)-unit partial record
 constexpr int RED_STEP = 0;      // record slots [0, 16): per-step sums (COMs, flags, L1 counts)
 constexpr int RED_DIAG = 16;     // record slots [16, 32): diagnostics sums
@@ -135,23 +90,27 @@ struct SysDesc {
     int32_t n_peunits, pad;
     int32_t npad, p1, nalloc, ntiles;  // sorted layout (see above)
     int32_t tunit_begin, pad2;         // prefix offset of this system's tiles in the launch
-    // symmetric FP32 kernel (Kahan mode): work units (row group g, chunk c) and reaction
-    // partials, per group g the tiles after its first row: 3 * TJ * sum_g (T - SYM_ROWS g - 1)
+    // symmetric kernels (FP32 Kahan and FP64 modes): work units (band g, chunk c) and reaction
+    // partials, per band g the tiles after its first row: 3 * TJ * sum_g (T - rows g - 1)
     int32_t *units;       // n_units pairs (g, c)
-    float *react;
+    float *react;         // (double * in the FP64 mode)
     int32_t ch, sym;      // tiles per chunk; 1 when the symmetric kernel is used
     void *vxs, *vys, *vzs;  // sorted velocities (eqs. 4-6 only; null otherwise)
-    int32_t law, pad3;
+    int32_t law, rows;    // element law; tile rows per band (1 in the FP64 mode)
 };
 
 // Kernel argument describing one launch over a segment table.
 struct Launch {
     const SysDesc *sys;
     int32_t n_sys;
-    int32_t total_units;   // force units: (i-block, j chunk) pairs
+    int32_t unit_base;     // first force unit of this launch (a force launch may cover a range)
+    int32_t total_units;   // force units: (i-block, j chunk) pairs; the launch ends before this
     int32_t total_ounits;  // O(N) units: 256 elements in element order
     int32_t total_tunits;  // tiles: 256 slots in sorted order
     int32_t law;           // element law of every system in the launch (NB_LAW_*)
+    // FP32 Kahan mode: the table is ordered by band height; systems with bands of 1, 2 and 4 rows
+    // own the force units [0, band_end[0]), [band_end[0], band_end[1]), [band_end[1], band_end[2])
+    int32_t band_end[3];
 };
 
 // Segment-table entries written on the device from the systems' own one-entry tables (each

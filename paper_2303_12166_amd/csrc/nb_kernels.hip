@@ -3,12 +3,12 @@
 // The O(N^2) all-pairs force evaluation (Methodology: every element moves only under the sum of
 // all pairwise element-element interactions) is the hot path. It runs on the FP32 vector ALUs:
 // the pair sum is not a dense contraction, so there is no MFMA here. The kernels that evaluate it:
-//   - k_force_sym (FP32, Kahan mode, the default): each unordered pair once, i in registers and
-//     the j sums rotating across the wave (see the section below), for both element laws;
-//   - k_force_f32 (FP32, plain mode): one-sided, each lane keeps KI i elements and the block
-//     streams 256-element SoA j tiles through LDS (broadcast ds_read_b128), one FP32 running sum;
-//   - k_force_sym64 (FP64 reference mode): the symmetric scheme in FP64, both element laws;
-//     k_force_f64, one-sided, takes its place in builds with two tile rows per block.
+//   - k_force_sym<KR> / k_force_sym_paper<KR> (FP32, Kahan mode, the default): each unordered
+//     pair once, bands of KR tile rows with one i element of each row per lane in registers and
+//     the j sums rotating across the wave (see the section below), contact law / eqs. (4)-(6);
+//   - k_force_f32 (FP32, plain mode): one-sided, one i element per lane, the block streams
+//     256-element SoA j tiles through LDS (broadcast ds_read_b128), one FP32 running sum;
+//   - k_force_sym64<LAW> (FP64 reference mode): the symmetric scheme in FP64, both element laws.
 // All of them work on a Morton-sorted, star-by-star padded copy of the positions; the FP32 ones
 // skip the contact test on tiles whose bounding boxes are at least D apart. Per pair of the
 // contact law:
@@ -187,16 +187,12 @@ __global__ __launch_bounds__(BT) void k_gather(Launch L)
 
 // ------------------------------------------------------------------ FP32 one-sided force kernel
 
-template <int KI>
-struct IState {
-    float x[KI], y[KI], z[KI];
-    float ax[KI], ay[KI], az[KI];
-};
-
-// Near tiles: the contact law s = min(w^3, c1 - c2 w) for every pair.
-template <int KI>
-__device__ __forceinline__ void interact4_near(const float4 &X, const float4 &Y, const float4 &Z,
-                                               IState<KI> &I, float c1, float nc2)
+// Near tiles: the contact law s = min(w^3, c1 - c2 w) for every pair; far tiles (every pair at
+// r >= D, proven from bounding boxes): s = w^3, the value the contact law's minimum selects there.
+template <bool FAR>
+__device__ __forceinline__ void interact4_f32(const float4 &X, const float4 &Y, const float4 &Z,
+                                              float xi, float yi, float zi, float &ax, float &ay,
+                                              float &az, float c1, float nc2)
 {
     const float eps = 1.0e-24f;
     const float xs[4] = {X.x, X.y, X.z, X.w};
@@ -204,112 +200,47 @@ __device__ __forceinline__ void interact4_near(const float4 &X, const float4 &Y,
     const float zs[4] = {Z.x, Z.y, Z.z, Z.w};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-#pragma unroll
-        for (int k = 0; k < KI; ++k) {
-            const float dx = xs[q] - I.x[k];
-            const float dy = ys[q] - I.y[k];
-            const float dz = zs[q] - I.z[k];
-            const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
-            const float w = __builtin_amdgcn_rsqf(r2);
-            const float w3 = (w * w) * w;
-            const float s = fminf(w3, fmaf(nc2, w, c1));
-            I.ax[k] = fmaf(s, dx, I.ax[k]);
-            I.ay[k] = fmaf(s, dy, I.ay[k]);
-            I.az[k] = fmaf(s, dz, I.az[k]);
-        }
-    }
-}
-
-// Far tiles (every pair at r >= D, proven from bounding boxes): s = w^3, the value the contact
-// law's minimum selects there.
-template <int KI>
-__device__ __forceinline__ void interact4_far(const float4 &X, const float4 &Y, const float4 &Z,
-                                              IState<KI> &I)
-{
-    const float eps = 1.0e-24f;
-    const float xs[4] = {X.x, X.y, X.z, X.w};
-    const float ys[4] = {Y.x, Y.y, Y.z, Y.w};
-    const float zs[4] = {Z.x, Z.y, Z.z, Z.w};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-#pragma unroll
-        for (int k = 0; k < KI; ++k) {
-            const float dx = xs[q] - I.x[k];
-            const float dy = ys[q] - I.y[k];
-            const float dz = zs[q] - I.z[k];
-            const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
-            const float w = __builtin_amdgcn_rsqf(r2);
-            const float s = (w * w) * w;
-            I.ax[k] = fmaf(s, dx, I.ax[k]);
-            I.ay[k] = fmaf(s, dy, I.ay[k]);
-            I.az[k] = fmaf(s, dz, I.az[k]);
-        }
+        const float dx = xs[q] - xi;
+        const float dy = ys[q] - yi;
+        const float dz = zs[q] - zi;
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
+        const float w = __builtin_amdgcn_rsqf(r2);
+        const float w3 = (w * w) * w;
+        const float s = FAR ? w3 : fminf(w3, fmaf(nc2, w, c1));
+        ax = fmaf(s, dx, ax);
+        ay = fmaf(s, dy, ay);
+        az = fmaf(s, dz, az);
     }
 }
 
 __device__ __forceinline__ float4 lds4(const float *p) { return *reinterpret_cast<const float4 *>(p); }
 
-template <int KI, bool FAR>
-__device__ __forceinline__ void interact_tile_f32(const float *__restrict__ sx,
-                                                  const float *__restrict__ sy,
-                                                  const float *__restrict__ sz, IState<KI> &I,
-                                                  float c1, float nc2)
-{
-#pragma unroll NB_JUNROLL
-    for (int jj = 0; jj < TJ; jj += 4) {
-        const float4 X = lds4(sx + jj), Y = lds4(sy + jj), Z = lds4(sz + jj);
-        if (FAR) {
-            interact4_far<KI>(X, Y, Z, I);
-        } else {
-            interact4_near<KI>(X, Y, Z, I, c1, nc2);
-        }
-    }
-}
-
-// One force unit: i-block `ib` (BT * KI sorted slots; each wave owns 64 * KI consecutive slots)
-// against j chunk `c` (a run of whole tiles).
-template <int KI, bool KAHAN>
+// One force unit of the plain mode: i-block `ib` (256 sorted slots, one per lane) against j
+// chunk `c` (a run of whole tiles), one running FP32 sum per element in tile order.
 __device__ __forceinline__ void force_unit_f32(const SysDesc &S, int ib, int c,
                                                float (*sh)[3][TJ])
 {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     const float *__restrict__ XS = static_cast<const float *>(S.xs);
     const float *__restrict__ YS = static_cast<const float *>(S.ys);
     const float *__restrict__ ZS = static_cast<const float *>(S.zs);
     const DevState *st = S.st;
 
-    IState<KI> I;
-    const int base = ib * (BT * KI) + wave * (64 * KI);
-    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-#pragma unroll
-    for (int k = 0; k < KI; ++k) {
-        const int slot = base + k * 64 + lane;
-        I.x[k] = XS[slot];
-        I.y[k] = YS[slot];
-        I.z[k] = ZS[slot];
-        I.ax[k] = I.ay[k] = I.az[k] = 0.0f;
-        if (S.perm[slot] >= 0) {
-            lo[0] = fminf(lo[0], I.x[k]);
-            lo[1] = fminf(lo[1], I.y[k]);
-            lo[2] = fminf(lo[2], I.z[k]);
-            hi[0] = fmaxf(hi[0], I.x[k]);
-            hi[1] = fmaxf(hi[1], I.y[k]);
-            hi[2] = fmaxf(hi[2], I.z[k]);
-        }
-    }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        lo[d] = wave_min(lo[d]);
-        hi[d] = wave_max(hi[d]);
-    }
-    // the wave's slots lie in one star (p1 is a multiple of TJ, waves own aligned 64 KI runs)
-    const int istar = base >= S.p1 ? 1 : 0;
+    const int slot = ib * BT + tid;
+    const float xi = XS[slot], yi = YS[slot], zi = ZS[slot];
+    float ax = 0.0f, ay = 0.0f, az = 0.0f;
+    const bool real = S.perm[slot] >= 0;
+    float lo[3], hi[3];
+    lo[0] = wave_min(real ? xi : INFINITY);
+    lo[1] = wave_min(real ? yi : INFINITY);
+    lo[2] = wave_min(real ? zi : INFINITY);
+    hi[0] = wave_max(real ? xi : -INFINITY);
+    hi[1] = wave_max(real ? yi : -INFINITY);
+    hi[2] = wave_max(real ? zi : -INFINITY);
+    // the block's slots lie in one star (p1 is a multiple of TJ)
+    const int istar = ib * BT >= S.p1 ? 1 : 0;
     const float c1a = st->c1f[istar], nc2a = -st->c2f[istar], far2a = st->far2f[istar];
     const float c1b = st->c1f[istar + 1], nc2b = -st->c2f[istar + 1], far2b = st->far2f[istar + 1];
-
-    float sumx[KI], sumy[KI], sumz[KI], cx[KI], cy[KI], cz[KI];
-#pragma unroll
-    for (int k = 0; k < KI; ++k) sumx[k] = sumy[k] = sumz[k] = cx[k] = cy[k] = cz[k] = 0.0f;
 
     // chunk c covers tiles [c ntiles / nsplit, (c + 1) ntiles / nsplit): sizes differ by <= 1
     const int t0 = (int)(((int64_t)c * S.ntiles) / S.nsplit);
@@ -338,207 +269,79 @@ __device__ __forceinline__ void force_unit_f32(const SysDesc &S, int ib, int c,
         const float gz = fmaxf(0.0f, fmaxf(bx[2] - hi[2], lo[2] - bx[6]));
         const float gap2 = gx * gx + gy * gy + gz * gz;
         const int far = __builtin_amdgcn_readfirstlane(gap2 >= (jstar ? far2b : far2a) ? 1 : 0);
+        const float *sx = sh[buf][0], *sy = sh[buf][1], *sz = sh[buf][2];
         if (far) {
-            interact_tile_f32<KI, true>(sh[buf][0], sh[buf][1], sh[buf][2], I, 0.f, 0.f);
+#pragma unroll 2
+            for (int jj = 0; jj < TJ; jj += 4)
+                interact4_f32<true>(lds4(sx + jj), lds4(sy + jj), lds4(sz + jj), xi, yi, zi, ax,
+                                    ay, az, 0.f, 0.f);
         } else {
-            interact_tile_f32<KI, false>(sh[buf][0], sh[buf][1], sh[buf][2], I,
-                                         jstar ? c1b : c1a, jstar ? nc2b : nc2a);
-        }
-        if (KAHAN) {
-#pragma unroll
-            for (int k = 0; k < KI; ++k) {
-                kahan_add(sumx[k], cx[k], I.ax[k]);
-                kahan_add(sumy[k], cy[k], I.ay[k]);
-                kahan_add(sumz[k], cz[k], I.az[k]);
-                I.ax[k] = I.ay[k] = I.az[k] = 0.0f;
-            }
+            const float c1 = jstar ? c1b : c1a, nc2 = jstar ? nc2b : nc2a;
+#pragma unroll 2
+            for (int jj = 0; jj < TJ; jj += 4)
+                interact4_f32<false>(lds4(sx + jj), lds4(sy + jj), lds4(sz + jj), xi, yi, zi, ax,
+                                     ay, az, c1, nc2);
         }
     }
     __syncthreads();  // the next unit of this block reuses both LDS buffers
 
-    const float gm = st->gm_f;
-#pragma unroll
-    for (int k = 0; k < KI; ++k) {
-        const int slot = base + k * 64 + lane;
-        const int idx = S.perm[slot];
-        if (idx < 0) continue;
-        float vx, vy, vz;
-        if (KAHAN) {
-            vx = sumx[k] - cx[k];
-            vy = sumy[k] - cy[k];
-            vz = sumz[k] - cz[k];
-        } else {
-            vx = I.ax[k];
-            vy = I.ay[k];
-            vz = I.az[k];
-        }
-        if (S.nsplit == 1) {
-            static_cast<float *>(S.ax)[idx] = gm * vx;
-            static_cast<float *>(S.ay)[idx] = gm * vy;
-            static_cast<float *>(S.az)[idx] = gm * vz;
-        } else {
-            float *P = static_cast<float *>(S.part);
-            const size_t na = S.nalloc;
-            const size_t b = (size_t)c * 3 * na + slot;
-            P[b] = vx;
-            P[b + na] = vy;
-            P[b + 2 * na] = vz;
-        }
+    const int idx = S.perm[slot];
+    if (idx < 0) return;
+    if (S.nsplit == 1) {
+        const float gm = st->gm_f;
+        static_cast<float *>(S.ax)[idx] = gm * ax;
+        static_cast<float *>(S.ay)[idx] = gm * ay;
+        static_cast<float *>(S.az)[idx] = gm * az;
+    } else {
+        float *P = static_cast<float *>(S.part);
+        const size_t na = S.nalloc;
+        const size_t b = (size_t)c * 3 * na + slot;
+        P[b] = ax;
+        P[b + na] = ay;
+        P[b + 2 * na] = az;
     }
 }
 
-template <int KI, bool KAHAN>
-__global__ __launch_bounds__(BT) NB_FORCE_ATTR void k_force_f32(Launch L)
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(PLAIN_WAVES)))
+void k_force_f32(Launch L)
 {
     __shared__ __attribute__((aligned(16))) float sh[2][3][TJ];
-    for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
+    for (int u = L.unit_base + blockIdx.x; u < L.total_units; u += gridDim.x) {
         const int s = find_sys(L, u, false);
         const SysDesc &S = L.sys[s];
         const int local = u - S.unit_begin;
         const int ib = local / S.nsplit;
         const int c = local - ib * S.nsplit;
-        force_unit_f32<KI, KAHAN>(S, ib, c, sh);
+        force_unit_f32(S, ib, c, sh);
     }
 }
 
 // ------------------------------------------------------------------ FP32 symmetric force kernel
 //
 // Newton's third law halves the pair work: the pair (i, j) with i in tile I and j in a later tile
-// J > I is evaluated once. Row I of the work is the 256 i slots of tile I against tiles I .. T-1,
-// cut into chunks of `ch` tiles. Within a wave each lane keeps one i element; a tile's 256 j
-// elements are taken as four groups of 64. At step s (0..63) lane l meets element (l - s) mod 64
-// of each group: its position is read from LDS at that rotating offset, and the j accumulator
-// travels with it, moved one lane per step by a DPP wave rotation fused into the update
-// a_j <- rotate(a_j) - s (r_j - r_i). After 64 steps (and one last rotation) every lane holds the
-// summed reaction of the wave's 64 i elements on its own j. The waves' sums are added in wave
-// order and stored as the reaction of the row (group) on those j. The diagonal tile J = I is
-// evaluated one-sided. k_combine_sym adds, per element, its own row's chunk partials and then
-// the reactions of every earlier row group, in that order, with Kahan compensation.
+// J > I is evaluated once. The tile rows are taken in groups ("row bands") of KR consecutive rows
+// (KR = 1, 2 or 4, chosen per system size): a work unit is group g, rows I = KR g .. KR g + KR - 1,
+// against chunk c of its tiles, a run of `ch` tiles starting at KR g + c ch. Each lane of the
+// block's four waves keeps one i element of every row of the band, at the same position in each
+// row. A tile's 256 j elements are taken as four groups of 64. At step s (0..63) lane l meets
+// element (l - s) mod 64 of each group: its position is read from LDS once at that rotating
+// offset and paired with the lane's KR i elements, and the j accumulator travels with it, moved
+// one lane per step by a DPP wave rotation fused into the first row's update
+// a_j <- rotate(a_j) - s (r_j - r_i); the other rows subtract their terms in row order. After 64
+// steps (and one last rotation) every lane holds the summed reaction of the wave's 64 KR i
+// elements on its own j. The waves' sums are added in wave order and stored once per
+// (group, tile): a band of KR rows stores 1/KR of the reaction blocks of single rows. Tiles inside
+// the band are split by row: tile KR g + k is one-sided for row k, full for the rows before it and
+// skipped by the rows after it. k_combine_sym adds, per element, its own row's chunk partials and
+// then the reactions of every group with a row before the element's tile, in group order, with
+// Kahan compensation. The order of every sum is fixed by the system's own size, so results do not
+// depend on scheduling or on the other systems of a launch.
 
 constexpr int DPP_WAVE_ROR1 = 0x13C;  // lane l receives lane l - 1 (mod 64)
-
-// LDS tile layout. With NB_SYM_DUP each group of 64 is stored twice in a row (128 entries), so
-// the rotating read of element (l - s) mod 64 becomes entry l + 64 - s with no wrap-around and
-// the per-step address is one subtraction.
-constexpr int SYM_GSTRIDE = NB_SYM_DUP ? 128 : 64;
-constexpr int SYM_TILE = 4 * SYM_GSTRIDE;
-
-__device__ __forceinline__ int sym_slot(int jj) { return (jj >> 6) * SYM_GSTRIDE + (jj & 63); }
 
 __device__ __forceinline__ float wave_ror1(float v)
 {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), DPP_WAVE_ROR1, 0xf, 0xf, true));
-}
-
-// Constants of one pair class for the FP32 kernels.
-struct LawF {
-    float c1, nc2;            // contact law: 11 / D^3 and -10 / D^2
-    float D, twoD, eps, gc, gcb;  // eqs. (4)-(6): see DevState
-};
-
-// Pair scalar s = f / (G m^2 r) of one pair; the caller adds s d to the i sum.
-//   contact law:  min(w^3, c1 - c2 w) near, w^3 far.
-//   eqs. (4)-(6): w / (r + eps)^2 - g (D - r)_+^2 (1 + 2 D w), g = gc for a converging pair
-//                 ((v_j - v_i).(r_j - r_i) < 0) and gcb otherwise; the overlap term is left out
-//                 on far tiles, where every pair has r >= D. (pi / 12) (D - r)^2 (r + 2D) is the
-//                 overlap volume of eq. (5) in factored form, so it has no cancellation near D.
-template <int LAW, bool NEAR>
-__device__ __forceinline__ float pair_s(float r2, float w, float dx, float dy, float dz,
-                                        const float4 &vj, const float4 &vi, const LawF &K)
-{
-#pragma clang fp contract(off)
-    if constexpr (LAW == 0) {
-        const float w3 = (w * w) * w;
-        return NEAR ? fminf(w3, fmaf(K.nc2, w, K.c1)) : w3;
-    } else {
-        const float r = r2 * w;
-        const float it = __builtin_amdgcn_rcpf(r + K.eps);
-        float s = (it * it) * w;
-        if constexpr (NEAR) {
-            const float dot = fmaf(vj.x - vi.x, dx, fmaf(vj.y - vi.y, dy, (vj.z - vi.z) * dz));
-            const float g = dot < 0.0f ? K.gc : K.gcb;
-            const float u = fmaxf(K.D - r, 0.0f);
-            s = s - ((g * u) * u) * fmaf(K.twoD, w, 1.0f);
-        }
-        return s;
-    }
-}
-
-// One-sided diagonal tile from an AoS LDS tile (x, y, z, unused). The self pair has d = 0; under
-// eqs. (4)-(6) it is also masked, since its overlap term is of order 1/eps.
-template <int LAW>
-__device__ __forceinline__ void diag_tile(const float4 *__restrict__ sj,
-                                          const float4 *__restrict__ sv, IState<1> &I,
-                                          const float4 &vi, const LawF &K)
-{
-    const float eps = 1.0e-24f;
-    const int self = threadIdx.x;
-#pragma unroll 4
-    for (int jj = 0; jj < TJ; ++jj) {
-        const float4 P = sj[sym_slot(jj)];
-        const float dx = P.x - I.x[0];
-        const float dy = P.y - I.y[0];
-        const float dz = P.z - I.z[0];
-        const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
-        const float w = __builtin_amdgcn_rsqf(r2);
-        float s;
-        if constexpr (LAW == 0) {
-            s = pair_s<0, true>(r2, w, dx, dy, dz, vi, vi, K);
-        } else {
-            s = pair_s<LAW, true>(r2, w, dx, dy, dz, sv[sym_slot(jj)], vi, K);
-            s = jj == self ? 0.0f : s;
-        }
-        I.ax[0] = fmaf(s, dx, I.ax[0]);
-        I.ay[0] = fmaf(s, dy, I.ay[0]);
-        I.az[0] = fmaf(s, dz, I.az[0]);
-    }
-}
-
-template <bool NEAR, int LAW>
-__device__ __forceinline__ void sym_tile(const float4 *__restrict__ sj,
-                                         const float4 *__restrict__ sv, IState<1> &I,
-                                         const float4 &vi, const LawF &K, float *rwx, float *rwy,
-                                         float *rwz, int lane)
-{
-    // keep p = s d and the rotated update a_j <- rotate(a_j) - p as separate operations, so that
-    // the rotation folds into the subtraction (a VOP2 instruction with a DPP source)
-#pragma clang fp contract(off)
-    const float eps = 1.0e-24f;
-    float ajx[4] = {0.f, 0.f, 0.f, 0.f}, ajy[4] = {0.f, 0.f, 0.f, 0.f};
-    float ajz[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll NB_SYM_UNROLL
-    for (int st = 0; st < 64; ++st) {
-        const int e = NB_SYM_DUP ? lane + 64 - st : (lane - st) & 63;
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const float4 P = sj[g * SYM_GSTRIDE + e];
-            const float dx = P.x - I.x[0];
-            const float dy = P.y - I.y[0];
-            const float dz = P.z - I.z[0];
-            const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
-            const float w = __builtin_amdgcn_rsqf(r2);
-            float s;
-            if constexpr (LAW != 0 && NEAR) {
-                s = pair_s<LAW, NEAR>(r2, w, dx, dy, dz, sv[g * SYM_GSTRIDE + e], vi, K);
-            } else {
-                s = pair_s<LAW, NEAR>(r2, w, dx, dy, dz, vi, vi, K);
-            }
-            const float px = s * dx, py = s * dy, pz = s * dz;
-            I.ax[0] += px;
-            I.ay[0] += py;
-            I.az[0] += pz;
-            ajx[g] = wave_ror1(ajx[g]) - px;
-            ajy[g] = wave_ror1(ajy[g]) - py;
-            ajz[g] = wave_ror1(ajz[g]) - pz;
-        }
-    }
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        // one more rotation brings element l's sum back to lane l
-        rwx[g * 64 + lane] = wave_ror1(ajx[g]);
-        rwy[g * 64 + lane] = wave_ror1(ajy[g]);
-        rwz[g * 64 + lane] = wave_ror1(ajz[g]);
-    }
 }
 
 // A value that is the same in every lane, moved to a scalar register.
@@ -546,6 +349,12 @@ __device__ __forceinline__ float wave_uniform(float v)
 {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
+
+// Constants of one pair class for the FP32 kernels.
+struct LawF {
+    float c1, nc2;            // contact law: 11 / D^3 and -10 / D^2
+    float D, twoD, eps, gc, gcb;  // eqs. (4)-(6): see DevState
+};
 
 __device__ __forceinline__ LawF law_uniform(LawF K)
 {
@@ -572,27 +381,165 @@ __device__ __forceinline__ LawF law_f(const DevState *st, int cls)
     return K;
 }
 
-// Reactions are stored per row group g (tile rows SYM_ROWS g .. SYM_ROWS g + SYM_ROWS - 1) for the
-// tiles t after the group's first row, t = SYM_ROWS g + 1 .. T - 1: three components one after the
-// other, each (T - SYM_ROWS g - 1) TJ floats. Group g starts after
-// sum_{g' < g} 3 TJ (T - SYM_ROWS g' - 1) = 3 TJ (g (T - 1) - SYM_ROWS g (g - 1) / 2) floats.
-__device__ __forceinline__ size_t react_group_offset(int g, int ntiles)
+// Pair scalar s = f / (G m^2 r) of one pair; the caller adds s d to the i sum.
+//   contact law:  min(w^3, c1 - c2 w) near, w^3 far.
+//   eqs. (4)-(6): w / (r + eps)^2 - g (D - r)_+^2 (1 + 2 D w), g = gc for a converging pair
+//                 ((v_j - v_i).(r_j - r_i) < 0) and gcb otherwise; the overlap term is left out
+//                 on far tiles, where every pair has r >= D. (pi / 12) (D - r)^2 (r + 2D) is the
+//                 overlap volume of eq. (5) in factored form, so it has no cancellation near D.
+// On a far tile the near form gives the same bits (the contact law's minimum picks w^3 by a margin
+// far above rounding once r^2 >= (1 + FAR_MARGIN) D^2; the overlap term is exactly 0 for r >= D),
+// so the near/far choice changes speed only.
+template <int LAW, bool NEAR>
+__device__ __forceinline__ float pair_s(float r2, float w, float dx, float dy, float dz,
+                                        const float4 &vj, const float4 &vi, const LawF &K)
 {
-    return (size_t)3 * TJ *
-           ((size_t)g * (ntiles - 1) - (size_t)SYM_ROWS * (size_t)g * (size_t)(g - 1) / 2);
+#pragma clang fp contract(off)
+    if constexpr (LAW == 0) {
+        const float w3 = (w * w) * w;
+        return NEAR ? fminf(w3, fmaf(K.nc2, w, K.c1)) : w3;
+    } else {
+        const float r = r2 * w;
+        const float it = __builtin_amdgcn_rcpf(r + K.eps);
+        float s = (it * it) * w;
+        if constexpr (NEAR) {
+            const float dot = fmaf(vj.x - vi.x, dx, fmaf(vj.y - vi.y, dy, (vj.z - vi.z) * dz));
+            const float g = dot < 0.0f ? K.gc : K.gcb;
+            const float u = fmaxf(K.D - r, 0.0f);
+            s = s - ((g * u) * u) * fmaf(K.twoD, w, 1.0f);
+        }
+        return s;
+    }
 }
 
-// One work unit of the symmetric kernel: row group g against chunk c of its tiles. The block
-// has SYM_ROWS x 4 waves; waves 4r .. 4r + 3 own the 256 slots of tile row I = SYM_ROWS g + r (one
-// i per lane). Each j tile t of the chunk is staged once in LDS for all rows; row I evaluates
-// t = I one-sided, t > I with reactions, and skips t < I. The reactions of all rows on tile t
-// are added (rows in order, waves in order within a row) and stored once per (group, tile).
+// The i side of a band: one element of each of KR tile rows per lane.
+template <int KR>
+struct Band {
+    float x[KR], y[KR], z[KR];     // positions
+    float ax[KR], ay[KR], az[KR];  // sums over the current tile
+    float4 v[KR];                  // half-step velocities (eqs. 4-6 only)
+};
+
+// One-sided diagonal tile of one row from an AoS LDS tile (x, y, z, unused). The self pair has
+// d = 0; under eqs. (4)-(6) it is also masked, since its overlap term is of order 1/eps.
 template <int LAW>
+__device__ __forceinline__ void diag_tile(const float4 *__restrict__ sj,
+                                          const float4 *__restrict__ sv, float xi, float yi,
+                                          float zi, const float4 &vi, const LawF &K, float &ax,
+                                          float &ay, float &az)
+{
+    const float eps = 1.0e-24f;
+    const int self = threadIdx.x;
+#pragma unroll 4
+    for (int jj = 0; jj < TJ; ++jj) {
+        const float4 P = sj[jj];
+        const float dx = P.x - xi;
+        const float dy = P.y - yi;
+        const float dz = P.z - zi;
+        const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
+        const float w = __builtin_amdgcn_rsqf(r2);
+        float s;
+        if constexpr (LAW == 0) {
+            s = pair_s<0, true>(r2, w, dx, dy, dz, vi, vi, K);
+        } else {
+            s = pair_s<LAW, true>(r2, w, dx, dy, dz, sv[jj], vi, K);
+            s = jj == self ? 0.0f : s;
+        }
+        ax = fmaf(s, dx, ax);
+        ay = fmaf(s, dy, ay);
+        az = fmaf(s, dz, az);
+    }
+}
+
+// A full tile against the band's rows 0 .. nact - 1 (all KR rows unless MASKED; nact >= 1), with
+// the reactions on the tile's 256 j left in the wave's rw slice.
+template <bool NEAR, int LAW, int KR, bool MASKED>
+__device__ __forceinline__ void sym_tile(const float4 *__restrict__ sj,
+                                         const float4 *__restrict__ sv, Band<KR> &B,
+                                         const LawF (&K)[KR], float *rwx, float *rwy, float *rwz,
+                                         int lane, int nact)
+{
+    // keep p = s d and the rotated update a_j <- rotate(a_j) - p as separate operations, so that
+    // the rotation folds into the subtraction (a VOP2 instruction with a DPP source)
+#pragma clang fp contract(off)
+    const float eps = 1.0e-24f;
+    float ajx[4] = {0.f, 0.f, 0.f, 0.f}, ajy[4] = {0.f, 0.f, 0.f, 0.f};
+    float ajz[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int st = 0; st < 64; ++st) {
+        const int e = (lane - st) & 63;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const float4 P = sj[g * 64 + e];
+            float4 Vj = make_float4(0.f, 0.f, 0.f, 0.f);
+            if constexpr (LAW != 0 && NEAR) Vj = sv[g * 64 + e];
+#pragma unroll
+            for (int r = 0; r < KR; ++r) {
+                if (MASKED && r >= nact) continue;  // wave-uniform
+                const float dx = P.x - B.x[r];
+                const float dy = P.y - B.y[r];
+                const float dz = P.z - B.z[r];
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
+                const float w = __builtin_amdgcn_rsqf(r2);
+                const float s = pair_s<LAW, NEAR>(r2, w, dx, dy, dz, Vj, B.v[r], K[r]);
+                const float px = s * dx, py = s * dy, pz = s * dz;
+                B.ax[r] += px;
+                B.ay[r] += py;
+                B.az[r] += pz;
+                if (r == 0) {
+                    ajx[g] = wave_ror1(ajx[g]) - px;
+                    ajy[g] = wave_ror1(ajy[g]) - py;
+                    ajz[g] = wave_ror1(ajz[g]) - pz;
+                } else {
+                    ajx[g] = ajx[g] - px;
+                    ajy[g] = ajy[g] - py;
+                    ajz[g] = ajz[g] - pz;
+                }
+                // contact law: keep each pair's instructions together. Left free, the scheduler
+                // gathers the twelve rotated updates of a step at its end, and back-to-back DPP
+                // subtractions issue at about a third of the rate of plain ones (measured 11 %
+                // slower at one row per band). The eqs. (4)-(6) loop measured 3.5 % faster
+                // without the barrier.
+                if constexpr (LAW == 0) __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        // one more rotation brings element l's sum back to lane l
+        rwx[g * 64 + lane] = wave_ror1(ajx[g]);
+        rwy[g * 64 + lane] = wave_ror1(ajy[g]);
+        rwz[g * 64 + lane] = wave_ror1(ajz[g]);
+    }
+}
+
+// Reactions are stored per group g (tile rows KR g .. KR g + KR - 1) for the tiles t after the
+// group's first row, t = KR g + 1 .. T - 1: three components one after the other, each
+// (T - KR g - 1) TJ values. Group g starts after
+// sum_{g' < g} 3 TJ (T - KR g' - 1) = 3 TJ (g (T - 1) - KR g (g - 1) / 2) values.
+__device__ __forceinline__ size_t react_group_offset(int g, int ntiles, int kr)
+{
+    return (size_t)3 * TJ *
+           ((size_t)g * (ntiles - 1) - (size_t)kr * (size_t)g * (size_t)(g - 1) / 2);
+}
+
+// Whether a tile lies at least D from every i of the wave (its bounding box against the wave's),
+// for the larger of the band's thresholds.
+__device__ __forceinline__ bool far_tile(const float *bx, const float (&lo)[3],
+                                         const float (&hi)[3], float far2)
+{
+    const float gx = fmaxf(0.0f, fmaxf(bx[0] - hi[0], lo[0] - bx[4]));
+    const float gy = fmaxf(0.0f, fmaxf(bx[1] - hi[1], lo[1] - bx[5]));
+    const float gz = fmaxf(0.0f, fmaxf(bx[2] - hi[2], lo[2] - bx[6]));
+    const float gap2 = gx * gx + gy * gy + gz * gz;
+    return __builtin_amdgcn_readfirstlane(gap2 >= far2 ? 1 : 0) != 0;
+}
+
+// One work unit of the symmetric kernel: band `grp` against chunk c of its tiles (see above).
+template <int LAW, int KR>
 __device__ void force_unit_sym(const SysDesc &S, int grp, int c, float4 *sj, float4 *sv,
                                float (*rw)[3][TJ])
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int r = tid / TJ, lt = tid % TJ;
     const float *__restrict__ XS = static_cast<const float *>(S.xs);
     const float *__restrict__ YS = static_cast<const float *>(S.ys);
     const float *__restrict__ ZS = static_cast<const float *>(S.zs);
@@ -601,248 +548,229 @@ __device__ void force_unit_sym(const SysDesc &S, int grp, int c, float4 *sj, flo
     const float *__restrict__ VZS = static_cast<const float *>(S.vzs);
     const DevState *st = S.st;
     const int T = S.ntiles;
-    const int g0 = SYM_ROWS * grp;            // first tile row of the group
-    const int I = g0 + r;                     // this wave's tile row
-    const bool row_ok = I < T;                // the last group may be short
-    const int slot = (row_ok ? I : g0) * TJ + lt;
-    IState<1> Ist;
-    Ist.x[0] = XS[slot];
-    Ist.y[0] = YS[slot];
-    Ist.z[0] = ZS[slot];
-    Ist.ax[0] = Ist.ay[0] = Ist.az[0] = 0.0f;
-    float4 vi = make_float4(0.f, 0.f, 0.f, 0.f);
-    if constexpr (LAW != 0) vi = make_float4(VXS[slot], VYS[slot], VZS[slot], 0.0f);
-    const bool real = row_ok && S.perm[slot] >= 0;
-    float lo[3], hi[3];
-    lo[0] = wave_min(real ? Ist.x[0] : INFINITY);
-    lo[1] = wave_min(real ? Ist.y[0] : INFINITY);
-    lo[2] = wave_min(real ? Ist.z[0] : INFINITY);
-    hi[0] = wave_max(real ? Ist.x[0] : -INFINITY);
-    hi[1] = wave_max(real ? Ist.y[0] : -INFINITY);
-    hi[2] = wave_max(real ? Ist.z[0] : -INFINITY);
-    const int istar = I * TJ >= S.p1 ? 1 : 0;
-    LawF Ka = law_f(st, istar), Kb = law_f(st, istar + 1);
-    float far2a = st->far2f[istar], far2b = st->far2f[istar + 1];
-    if constexpr (LAW != 0) {
-        // the box and the constants are the same in every lane; held in scalar registers they
-        // leave the eqs. (4)-(6) kernel enough vector registers for six waves per SIMD without
-        // spilling
-        for (int d = 0; d < 3; ++d) {
-            lo[d] = wave_uniform(lo[d]);
-            hi[d] = wave_uniform(hi[d]);
+    const int g0 = KR * grp;               // first tile row of the band
+    const int nv = min(KR, T - g0);        // rows of the band inside the system (the last is short)
+    Band<KR> B;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    LawF Ka[KR], Kb[KR];
+    float far2a = 0.0f, far2b = 0.0f;
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        const int row = r < nv ? g0 + r : g0;  // a missing row mirrors row 0 and stays unused
+        const int slot = row * TJ + tid;
+        B.x[r] = XS[slot];
+        B.y[r] = YS[slot];
+        B.z[r] = ZS[slot];
+        B.ax[r] = B.ay[r] = B.az[r] = 0.0f;
+        B.v[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if constexpr (LAW != 0) B.v[r] = make_float4(VXS[slot], VYS[slot], VZS[slot], 0.0f);
+        if (r < nv && S.perm[slot] >= 0) {
+            lo[0] = fminf(lo[0], B.x[r]);
+            lo[1] = fminf(lo[1], B.y[r]);
+            lo[2] = fminf(lo[2], B.z[r]);
+            hi[0] = fmaxf(hi[0], B.x[r]);
+            hi[1] = fmaxf(hi[1], B.y[r]);
+            hi[2] = fmaxf(hi[2], B.z[r]);
         }
-        Ka = law_uniform(Ka);
-        Kb = law_uniform(Kb);
-        far2a = wave_uniform(far2a);
-        far2b = wave_uniform(far2b);
+        const int istar = row * TJ >= S.p1 ? 1 : 0;
+        Ka[r] = law_uniform(law_f(st, istar));
+        Kb[r] = law_uniform(law_f(st, istar + 1));
+        far2a = fmaxf(far2a, st->far2f[istar]);
+        far2b = fmaxf(far2b, st->far2f[istar + 1]);
     }
+    // the box and the constants are the same in every lane; held in scalar registers they leave
+    // the vector registers to the pair loop
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = wave_uniform(wave_min(lo[d]));
+        hi[d] = wave_uniform(wave_max(hi[d]));
+    }
+    far2a = wave_uniform(far2a);
+    far2b = wave_uniform(far2b);
 
-    float sumx = 0.f, sumy = 0.f, sumz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+    float sumx[KR], sumy[KR], sumz[KR], cx[KR], cy[KR], cz[KR];
+#pragma unroll
+    for (int r = 0; r < KR; ++r) sumx[r] = sumy[r] = sumz[r] = cx[r] = cy[r] = cz[r] = 0.0f;
     const int t0 = g0 + c * S.ch;
     const int t1 = min(T, t0 + S.ch);
     float *R = S.react;
-    const size_t roff = react_group_offset(grp, T);
+    const size_t roff = react_group_offset(grp, T, KR);
     const size_t rlen = (size_t)(T - g0 - 1) * TJ;
-    // tile staging: with one row per block every thread loads its slot's position (and
-    // velocity); with two, the first row's threads load positions and the second's velocities
-    const bool load_pos = SYM_ROWS == 1 || r == 0;
-    const bool load_vel = LAW != 0 && (SYM_ROWS == 1 || r == 1);
     float px = 0.f, py = 0.f, pz = 0.f, qx = 0.f, qy = 0.f, qz = 0.f;
     if (t0 < t1) {
-        if (load_pos) {
-            px = XS[t0 * TJ + lt];
-            py = YS[t0 * TJ + lt];
-            pz = ZS[t0 * TJ + lt];
-        }
-        if (load_vel) {
-            qx = VXS[t0 * TJ + lt];
-            qy = VYS[t0 * TJ + lt];
-            qz = VZS[t0 * TJ + lt];
+        px = XS[t0 * TJ + tid];
+        py = YS[t0 * TJ + tid];
+        pz = ZS[t0 * TJ + tid];
+        if constexpr (LAW != 0) {
+            qx = VXS[t0 * TJ + tid];
+            qy = VYS[t0 * TJ + tid];
+            qz = VZS[t0 * TJ + tid];
         }
     }
     for (int t = t0; t < t1; ++t) {
-        {
-            const int at = sym_slot(lt);
-            if (load_pos) {
-                sj[at] = make_float4(px, py, pz, 0.0f);
-                if constexpr (NB_SYM_DUP != 0) sj[at + 64] = make_float4(px, py, pz, 0.0f);
-            }
-            if (load_vel) {
-                sv[at] = make_float4(qx, qy, qz, 0.0f);
-                if constexpr (NB_SYM_DUP != 0) sv[at + 64] = make_float4(qx, qy, qz, 0.0f);
-            }
-        }
+        sj[tid] = make_float4(px, py, pz, 0.0f);
+        if constexpr (LAW != 0) sv[tid] = make_float4(qx, qy, qz, 0.0f);
         __syncthreads();
         if (t + 1 < t1) {
-            if (load_pos) {
-                px = XS[(t + 1) * TJ + lt];
-                py = YS[(t + 1) * TJ + lt];
-                pz = ZS[(t + 1) * TJ + lt];
-            }
-            if (load_vel) {
-                qx = VXS[(t + 1) * TJ + lt];
-                qy = VYS[(t + 1) * TJ + lt];
-                qz = VZS[(t + 1) * TJ + lt];
+            px = XS[(t + 1) * TJ + tid];
+            py = YS[(t + 1) * TJ + tid];
+            pz = ZS[(t + 1) * TJ + tid];
+            if constexpr (LAW != 0) {
+                qx = VXS[(t + 1) * TJ + tid];
+                qy = VYS[(t + 1) * TJ + tid];
+                qz = VZS[(t + 1) * TJ + tid];
             }
         }
         const bool jstar = t * TJ >= S.p1;
-        LawF K;
-        K.c1 = jstar ? Kb.c1 : Ka.c1;
-        K.nc2 = jstar ? Kb.nc2 : Ka.nc2;
-        K.D = jstar ? Kb.D : Ka.D;
-        K.twoD = jstar ? Kb.twoD : Ka.twoD;
-        K.eps = Ka.eps;
-        K.gc = Ka.gc;
-        K.gcb = Ka.gcb;
-        if (row_ok && t == I) {
-            diag_tile<LAW>(sj, sv, Ist, vi, K);
-        } else if (row_ok && t > I) {
-            const float *bx = S.tbox + (size_t)t * 8;
-            const float gx = fmaxf(0.0f, fmaxf(bx[0] - hi[0], lo[0] - bx[4]));
-            const float gy = fmaxf(0.0f, fmaxf(bx[1] - hi[1], lo[1] - bx[5]));
-            const float gz = fmaxf(0.0f, fmaxf(bx[2] - hi[2], lo[2] - bx[6]));
-            const float gap2 = gx * gx + gy * gy + gz * gz;
-            const int far = __builtin_amdgcn_readfirstlane(gap2 >= (jstar ? far2b : far2a) ? 1 : 0);
-            if (far) {
-                sym_tile<false, LAW>(sj, sv, Ist, vi, K, rw[wave][0], rw[wave][1], rw[wave][2],
-                                     lane);
+        LawF K[KR];
+#pragma unroll
+        for (int r = 0; r < KR; ++r) K[r] = jstar ? Kb[r] : Ka[r];
+        const float far2 = jstar ? far2b : far2a;
+        const int k = t - g0;  // tile t is row k of the band when k < KR
+        if (k >= KR) {
+            if (far_tile(S.tbox + (size_t)t * 8, lo, hi, far2)) {
+                sym_tile<false, LAW, KR, false>(sj, sv, B, K, rw[wave][0], rw[wave][1],
+                                                rw[wave][2], lane, KR);
             } else {
-                sym_tile<true, LAW>(sj, sv, Ist, vi, K, rw[wave][0], rw[wave][1], rw[wave][2],
-                                    lane);
+                sym_tile<true, LAW, KR, false>(sj, sv, B, K, rw[wave][0], rw[wave][1],
+                                               rw[wave][2], lane, KR);
+            }
+        } else {
+            if (k > 0) {
+                // rows 0 .. k - 1 lie before tile t: full pairs with reactions
+                sym_tile<true, LAW, KR, true>(sj, sv, B, K, rw[wave][0], rw[wave][1], rw[wave][2],
+                                              lane, k);
+            }
+#pragma unroll
+            for (int r = 0; r < KR; ++r) {
+                if (r == k) {
+                    diag_tile<LAW>(sj, sv, B.x[r], B.y[r], B.z[r], B.v[r], K[r], B.ax[r], B.ay[r],
+                                   B.az[r]);
+                }
             }
         }
         if (t > g0) {
-            // tile t lies after the group's first row, so at least one row left reactions
+            // tile t lies after the band's first row, so at least one row left reactions
             __syncthreads();
-            if (tid < TJ) {
-                const size_t at = roff + (size_t)(t - g0 - 1) * TJ + lt;
+            const size_t at = roff + (size_t)(t - g0 - 1) * TJ + tid;
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    float v = ((rw[0][d][lt] + rw[1][d][lt]) + rw[2][d][lt]) + rw[3][d][lt];
-#pragma unroll
-                    for (int q = 1; q < SYM_ROWS; ++q) {
-                        if (t > g0 + q && g0 + q < T) {
-                            v = (((v + rw[4 * q][d][lt]) + rw[4 * q + 1][d][lt]) +
-                                 rw[4 * q + 2][d][lt]) + rw[4 * q + 3][d][lt];
-                        }
-                    }
-                    R[at + d * rlen] = v;
-                }
-            }
+            for (int d = 0; d < 3; ++d)
+                R[at + d * rlen] = ((rw[0][d][tid] + rw[1][d][tid]) + rw[2][d][tid]) + rw[3][d][tid];
         }
-        kahan_add(sumx, cx, Ist.ax[0]);
-        kahan_add(sumy, cy, Ist.ay[0]);
-        kahan_add(sumz, cz, Ist.az[0]);
-        Ist.ax[0] = Ist.ay[0] = Ist.az[0] = 0.0f;
+#pragma unroll
+        for (int r = 0; r < KR; ++r) {
+            kahan_add(sumx[r], cx[r], B.ax[r]);
+            kahan_add(sumy[r], cy[r], B.ay[r]);
+            kahan_add(sumz[r], cz[r], B.az[r]);
+            B.ax[r] = B.ay[r] = B.az[r] = 0.0f;
+        }
         __syncthreads();  // sj, sv and rw are rewritten by the next tile
     }
-    if (real) {
-        float *P = static_cast<float *>(S.part);
-        const size_t na = S.nalloc;
+    float *P = static_cast<float *>(S.part);
+    const size_t na = S.nalloc;
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        if (r >= nv) continue;
+        const int slot = (g0 + r) * TJ + tid;
+        if (S.perm[slot] < 0) continue;
         const size_t b = (size_t)c * 3 * na + slot;
-        P[b] = sumx - cx;
-        P[b + na] = sumy - cy;
-        P[b + 2 * na] = sumz - cz;
+        P[b] = sumx[r] - cx[r];
+        P[b + na] = sumy[r] - cy[r];
+        P[b + 2 * na] = sumz[r] - cz[r];
     }
 }
 
-__global__ __launch_bounds__(BT * SYM_ROWS) NB_SYM_ATTR void k_force_sym(Launch L)
+template <int LAW, int KR>
+__device__ __forceinline__ void force_sym_units(const Launch &L, float4 *sj, float4 *sv,
+                                                float (*rw)[3][TJ])
 {
-    __shared__ float4 sj[SYM_TILE];
-    __shared__ __attribute__((aligned(16))) float rw[4 * SYM_ROWS][3][TJ];
-    for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
+    for (int u = L.unit_base + blockIdx.x; u < L.total_units; u += gridDim.x) {
         const SysDesc &S = L.sys[find_sys(L, u, false)];
-        const int2 ic = reinterpret_cast<const int2 *>(S.units)[u - S.unit_begin];
-        force_unit_sym<0>(S, ic.x, ic.y, sj, nullptr, rw);
+        const int2 gc = reinterpret_cast<const int2 *>(S.units)[u - S.unit_begin];
+        force_unit_sym<LAW, KR>(S, gc.x, gc.y, sj, sv, rw);
     }
+}
+
+// Contact law; the launch covers the units [unit_base, total_units) of systems with KR rows per
+// band (the runtime orders a segment table by band height, so each height is one range).
+template <int KR>
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(SYM_WAVES[KR / 2])))
+void k_force_sym(Launch L)
+{
+    __shared__ float4 sj[TJ];
+    __shared__ __attribute__((aligned(16))) float rw[4][3][TJ];
+    force_sym_units<0, KR>(L, sj, nullptr, rw);
 }
 
 // The same under eqs. (4)-(6): each tile also stages the sorted half-step velocities.
-__global__ __launch_bounds__(BT * SYM_ROWS) NB_SYM_PAPER_ATTR void k_force_sym_paper(Launch L)
+template <int KR>
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(SYM_PAPER_WAVES[KR / 2])))
+void k_force_sym_paper(Launch L)
 {
-    __shared__ float4 sj[SYM_TILE];
-    __shared__ float4 sv[SYM_TILE];
-    __shared__ __attribute__((aligned(16))) float rw[4 * SYM_ROWS][3][TJ];
-    for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
-        const SysDesc &S = L.sys[find_sys(L, u, false)];
-        const int2 ic = reinterpret_cast<const int2 *>(S.units)[u - S.unit_begin];
-        force_unit_sym<1>(S, ic.x, ic.y, sj, sv, rw);
-    }
+    __shared__ float4 sj[TJ];
+    __shared__ float4 sv[TJ];
+    __shared__ __attribute__((aligned(16))) float rw[4][3][TJ];
+    force_sym_units<1, KR>(L, sj, sv, rw);
 }
 
-// a = G m (sum of the element's own chunk partials, then the reactions of every row group with a
-// row before the element's tile, in group order), scattered to the element's own index. Each
-// element's groups are cut into SEGS contiguous runs, summed by SEGS threads at once; each run is
-// a Kahan sum in group order (the first run starts with the chunk partials), and the run
-// results are added in run order with Kahan compensation. The order is fixed, so the result is
-// too.
-template <int SEGS>
-__global__ __launch_bounds__(BT * SEGS) void k_combine_sym(Launch L)
+// a = G m (sum of the element's own chunk partials, then the reactions of every band with a
+// row before the element's tile, in band order), one Kahan sum per component, scattered to the
+// element's own index. KR is the system's band height.
+template <int KR>
+__device__ __forceinline__ void combine_tile(const SysDesc &S, int J, int e)
 {
-    __shared__ float part[SEGS > 1 ? SEGS : 1][3][BT];
-    const int e = threadIdx.x % BT, k = threadIdx.x / BT;
+    const int T = S.ntiles;
+    const int slot = J * TJ + e;
+    const int idx = S.perm[slot];
+    if (idx < 0) return;
+    const float *P = static_cast<const float *>(S.part);
+    const float *R = S.react;
+    const size_t na = S.nalloc;
+    const int own = J / KR;                           // the element's own band
+    const int cj = (T - KR * own + S.ch - 1) / S.ch;  // its chunk count
+    const int ng = (J + KR - 1) / KR;                 // bands with a row before J
+    float out[3];
+    for (int d = 0; d < 3; ++d) {
+        float sum = 0.f, comp = 0.f;
+        for (int c = 0; c < cj; ++c) kahan_add(sum, comp, P[(size_t)c * 3 * na + d * na + slot]);
+        // bands are read eight at a time (independent loads in flight), then added in band
+        // order; the arithmetic is the same as one band at a time
+        size_t off = 0;
+        size_t len = (size_t)(T - 1) * TJ;
+        int g = 0;
+        for (; g + 8 <= ng; g += 8) {
+            float v[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                v[q] = R[off + d * len + slot - (size_t)TJ * (KR * (g + q) + 1)];
+                off += 3 * len;
+                len -= (size_t)KR * TJ;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) kahan_add(sum, comp, v[q]);
+        }
+        for (; g < ng; ++g) {
+            kahan_add(sum, comp, R[off + d * len + slot - (size_t)TJ * (KR * g + 1)]);
+            off += 3 * len;
+            len -= (size_t)KR * TJ;
+        }
+        out[d] = sum - comp;
+    }
+    const float gm = S.st->gm_f;
+    static_cast<float *>(S.ax)[idx] = gm * out[0];
+    static_cast<float *>(S.ay)[idx] = gm * out[1];
+    static_cast<float *>(S.az)[idx] = gm * out[2];
+}
+
+__global__ __launch_bounds__(BT) void k_combine_sym(Launch L)
+{
     for (int u = blockIdx.x; u < L.total_tunits; u += gridDim.x) {
         const SysDesc &S = L.sys[find_tile_sys(L, u)];
         const int J = u - S.tunit_begin;
-        const int T = S.ntiles;
-        const int slot = J * TJ + e;
-        const int idx = S.perm[slot];
-        const float *P = static_cast<const float *>(S.part);
-        const float *R = S.react;
-        const size_t na = S.nalloc;
-        const int own = J / SYM_ROWS;                        // the element's own group
-        const int cj = (T - SYM_ROWS * own + S.ch - 1) / S.ch;  // its chunk count
-        const int ng = (J + SYM_ROWS - 1) / SYM_ROWS;          // groups with a row before J
-        const int r0 = (int)(((int64_t)ng * k) / SEGS), r1 = (int)(((int64_t)ng * (k + 1)) / SEGS);
-        float out[3] = {0.f, 0.f, 0.f};
-        if (idx >= 0) {
-            for (int d = 0; d < 3; ++d) {
-                float sum = 0.f, comp = 0.f;
-                if (k == 0) {
-                    for (int c = 0; c < cj; ++c)
-                        kahan_add(sum, comp, P[(size_t)c * 3 * na + d * na + slot]);
-                }
-                // groups are read eight at a time (independent loads in flight), then added in
-                // group order; the arithmetic is the same as one group at a time
-                size_t off = react_group_offset(r0, T);
-                size_t len = (size_t)(T - SYM_ROWS * r0 - 1) * TJ;
-                int g = r0;
-                for (; g + 8 <= r1; g += 8) {
-                    float v[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        v[q] = R[off + d * len + slot - (size_t)TJ * (SYM_ROWS * (g + q) + 1)];
-                        off += 3 * len;
-                        len -= (size_t)SYM_ROWS * TJ;
-                    }
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) kahan_add(sum, comp, v[q]);
-                }
-                for (; g < r1; ++g) {
-                    kahan_add(sum, comp, R[off + d * len + slot - (size_t)TJ * (SYM_ROWS * g + 1)]);
-                    off += 3 * len;
-                    len -= (size_t)SYM_ROWS * TJ;
-                }
-                out[d] = sum - comp;
-            }
-        }
-        if constexpr (SEGS > 1) {
-            for (int d = 0; d < 3; ++d) part[k][d][e] = out[d];
-            __syncthreads();
-            if (k == 0 && idx >= 0) {
-                for (int d = 0; d < 3; ++d) {
-                    float sum = out[d], comp = 0.f;
-                    for (int q = 1; q < SEGS; ++q) kahan_add(sum, comp, part[q][d][e]);
-                    out[d] = sum - comp;
-                }
-            }
-            __syncthreads();
-        }
-        if (k == 0 && idx >= 0) {
-            const float gm = S.st->gm_f;
-            static_cast<float *>(S.ax)[idx] = gm * out[0];
-            static_cast<float *>(S.ay)[idx] = gm * out[1];
-            static_cast<float *>(S.az)[idx] = gm * out[2];
+        switch (S.rows) {
+        case 1: combine_tile<1>(S, J, threadIdx.x); break;
+        case 2: combine_tile<2>(S, J, threadIdx.x); break;
+        default: combine_tile<4>(S, J, threadIdx.x); break;
         }
     }
 }
@@ -881,93 +809,6 @@ __device__ __forceinline__ double pair_s64(double r2, double w, double dx, doubl
             s -= g * u * u * (1.0 + 2.0 * D * w);
         }
         return s;
-    }
-}
-
-template <int LAW>
-__device__ void force_unit_f64(const SysDesc &S, int ib, int c, double (*sh)[TJ])
-{
-    const int tid = threadIdx.x;
-    const double *__restrict__ XS = static_cast<const double *>(S.xs);
-    const double *__restrict__ YS = static_cast<const double *>(S.ys);
-    const double *__restrict__ ZS = static_cast<const double *>(S.zs);
-    const double *__restrict__ VXS = static_cast<const double *>(S.vxs);
-    const double *__restrict__ VYS = static_cast<const double *>(S.vys);
-    const double *__restrict__ VZS = static_cast<const double *>(S.vzs);
-    const DevState *st = S.st;
-    const int slot = ib * BT + tid;
-    const double xi = XS[slot], yi = YS[slot], zi = ZS[slot];
-    double vxi = 0.0, vyi = 0.0, vzi = 0.0;
-    if constexpr (LAW != 0) {
-        vxi = VXS[slot];
-        vyi = VYS[slot];
-        vzi = VZS[slot];
-    }
-    const int istar = ib * BT >= S.p1 ? 1 : 0;
-    double ax = 0.0, ay = 0.0, az = 0.0;
-    const int t0 = (int)(((int64_t)c * S.ntiles) / S.nsplit);
-    const int t1 = (int)(((int64_t)(c + 1) * S.ntiles) / S.nsplit);
-    for (int t = t0; t < t1; ++t) {
-        sh[0][tid] = XS[t * TJ + tid];
-        sh[1][tid] = YS[t * TJ + tid];
-        sh[2][tid] = ZS[t * TJ + tid];
-        if constexpr (LAW != 0) {
-            sh[3][tid] = VXS[t * TJ + tid];
-            sh[4][tid] = VYS[t * TJ + tid];
-            sh[5][tid] = VZS[t * TJ + tid];
-        }
-        __syncthreads();
-        const int cls = pair_class(istar, t * TJ >= S.p1 ? 1 : 0);
-        const double c1 = st->c1d[cls], c2 = st->c2d[cls];
-        const double D = cls == 0 ? st->D1 : (cls == 2 ? st->D2 : 0.5 * (st->D1 + st->D2));
-        for (int jj = 0; jj < TJ; ++jj) {
-            const double dx = sh[0][jj] - xi;
-            const double dy = sh[1][jj] - yi;
-            const double dz = sh[2][jj] - zi;
-            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-            const double w = r2 > 0.0 ? rsqrt_f64(r2) : 0.0;
-            double s;
-            if constexpr (LAW == 0) {
-                s = pair_s64<0>(r2, w, dx, dy, dz, 0.0, 0.0, 0.0, D, c1, c2, st);
-            } else {
-                s = pair_s64<LAW>(r2, w, dx, dy, dz, sh[3][jj] - vxi, sh[4][jj] - vyi,
-                                  sh[5][jj] - vzi, D, c1, c2, st);
-            }
-            ax = fma(s, dx, ax);
-            ay = fma(s, dy, ay);
-            az = fma(s, dz, az);
-        }
-        __syncthreads();
-    }
-    const int idx = S.perm[slot];
-    if (idx >= 0) {
-        if (S.nsplit == 1) {
-            const double gm = st->gm_d;
-            static_cast<double *>(S.ax)[idx] = gm * ax;
-            static_cast<double *>(S.ay)[idx] = gm * ay;
-            static_cast<double *>(S.az)[idx] = gm * az;
-        } else {
-            double *P = static_cast<double *>(S.part);
-            const size_t na = S.nalloc;
-            const size_t b = (size_t)c * 3 * na + slot;
-            P[b] = ax;
-            P[b + na] = ay;
-            P[b + 2 * na] = az;
-        }
-    }
-}
-
-template <int LAW>
-__global__ __launch_bounds__(BT) void k_force_f64(Launch L)
-{
-    __shared__ double sh[LAW == 0 ? 3 : 6][TJ];
-    for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
-        const int s = find_sys(L, u, false);
-        const SysDesc &S = L.sys[s];
-        const int local = u - S.unit_begin;
-        const int ib = local / S.nsplit;
-        const int c = local - ib * S.nsplit;
-        force_unit_f64<LAW>(S, ib, c, sh);
     }
 }
 
@@ -1035,7 +876,7 @@ __device__ void force_unit_sym64(const SysDesc &S, int I, int c, double (*sj)[TJ
     const int t0 = I + c * S.ch;
     const int t1 = min(T, t0 + S.ch);
     double *R = reinterpret_cast<double *>(S.react);
-    const size_t roff = react_group_offset(I, T);
+    const size_t roff = react_group_offset(I, T, 1);
     const size_t rlen = (size_t)(T - I - 1) * TJ;
     for (int t = t0; t < t1; ++t) {
         sj[0][tid] = XS[t * TJ + tid];
@@ -1109,7 +950,7 @@ __global__ __launch_bounds__(BT) void k_force_sym64(Launch L)
     __shared__ double sj[3][TJ];
     __shared__ double sv[LAW == 0 ? 1 : 3][TJ];
     __shared__ double rw[4][3][TJ];
-    for (int u = blockIdx.x; u < L.total_units; u += gridDim.x) {
+    for (int u = L.unit_base + blockIdx.x; u < L.total_units; u += gridDim.x) {
         const SysDesc &S = L.sys[find_sys(L, u, false)];
         const int2 ic = reinterpret_cast<const int2 *>(S.units)[u - S.unit_begin];
         force_unit_sym64<LAW>(S, ic.x, ic.y, sj, sv, rw);
@@ -1167,10 +1008,9 @@ __global__ __launch_bounds__(BT) void k_combine_sym64(Launch L)
 
 // ------------------------------------------------------------------ j-split combine
 
-// Sums the chunk partials of each sorted slot in chunk order and scatters a = G m sum to the
-// element's own index.
-template <typename T, bool KAHAN>
-__global__ __launch_bounds__(BT) void k_combine(Launch L)
+// Plain mode: sums the chunk partials of each sorted slot in chunk order (plain FP32) and
+// scatters a = G m sum to the element's own index.
+__global__ __launch_bounds__(BT) void k_combine_f32(Launch L)
 {
     for (int u = blockIdx.x; u < L.total_tunits; u += gridDim.x) {
         const SysDesc &S = L.sys[find_tile_sys(L, u)];
@@ -1178,33 +1018,18 @@ __global__ __launch_bounds__(BT) void k_combine(Launch L)
         const int slot = (u - S.tunit_begin) * TJ + threadIdx.x;
         const int idx = S.perm[slot];
         if (idx < 0) continue;
-        const T *P = static_cast<const T *>(S.part);
+        const float *P = static_cast<const float *>(S.part);
         const size_t na = S.nalloc;
-        T out[3];
+        float out[3];
         for (int d = 0; d < 3; ++d) {
-            T sum = 0, comp = 0;
-            for (int c = 0; c < S.nsplit; ++c) {
-                const T v = P[(size_t)c * 3 * na + d * na + slot];
-                if (KAHAN) {
-                    const T y = v - comp;
-                    const T t = sum + y;
-                    comp = (t - sum) - y;
-                    sum = t;
-                } else {
-                    sum += v;
-                }
-            }
-            out[d] = KAHAN ? sum - comp : sum;
+            float sum = 0.0f;
+            for (int c = 0; c < S.nsplit; ++c) sum += P[(size_t)c * 3 * na + d * na + slot];
+            out[d] = sum;
         }
-        T gm;
-        if constexpr (sizeof(T) == 4) {
-            gm = S.st->gm_f;
-        } else {
-            gm = S.st->gm_d;
-        }
-        static_cast<T *>(S.ax)[idx] = gm * out[0];
-        static_cast<T *>(S.ay)[idx] = gm * out[1];
-        static_cast<T *>(S.az)[idx] = gm * out[2];
+        const float gm = S.st->gm_f;
+        static_cast<float *>(S.ax)[idx] = gm * out[0];
+        static_cast<float *>(S.ay)[idx] = gm * out[1];
+        static_cast<float *>(S.az)[idx] = gm * out[2];
     }
 }
 
@@ -1710,33 +1535,47 @@ hipError_t launch_gather(const Launch &L, int mode, hipStream_t s)
 hipError_t launch_forces(const Launch &L, int mode, int max_blocks, hipStream_t s)
 {
     if (L.total_units == 0) return hipSuccess;
-    // max_blocks > 0: persistent launch, each block loops over units u, u + grid, ...
-    const int blocks = max_blocks > 0 ? std::min(L.total_units, max_blocks) : L.total_units;
-    const dim3 g(grid_for(blocks)), b(BT);
     if (L.law != 0 && L.law != 1) return hipErrorInvalidValue;
+    // max_blocks > 0: persistent launch, each block loops over units u, u + grid, ...
+    auto grid = [&](int units) {
+        return dim3(grid_for(max_blocks > 0 ? std::min(units, max_blocks) : units));
+    };
+    Launch R = L;
+    R.unit_base = 0;
     if (mode == 0) {
         if (L.law != 0) return hipErrorInvalidValue;  // eqs. (4)-(6) have no plain FP32 kernel
-        hipLaunchKernelGGL((k_force_f32<KI32, false>), g, b, 0, s, L);
-    } else if (mode == 1) {
-        if (L.law == 0) {
-            hipLaunchKernelGGL(k_force_sym, g, dim3(BT * SYM_ROWS), 0, s, L);
-        } else {
-            hipLaunchKernelGGL(k_force_sym_paper, g, dim3(BT * SYM_ROWS), 0, s, L);
-        }
-    } else if (FP64_SYM) {
-        if (L.law == 0) {
-            hipLaunchKernelGGL(k_force_sym64<0>, g, b, 0, s, L);
-        } else {
-            hipLaunchKernelGGL(k_force_sym64<1>, g, b, 0, s, L);
-        }
-    } else {
-        if (L.law == 0) {
-            hipLaunchKernelGGL(k_force_f64<0>, g, b, 0, s, L);
-        } else {
-            hipLaunchKernelGGL(k_force_f64<1>, g, b, 0, s, L);
-        }
+        hipLaunchKernelGGL(k_force_f32, grid(L.total_units), dim3(BT), 0, s, R);
+        return hipGetLastError();
     }
-    return hipGetLastError();
+    if (mode == 2) {
+        if (L.law == 0) {
+            hipLaunchKernelGGL(k_force_sym64<0>, grid(L.total_units), dim3(BT), 0, s, R);
+        } else {
+            hipLaunchKernelGGL(k_force_sym64<1>, grid(L.total_units), dim3(BT), 0, s, R);
+        }
+        return hipGetLastError();
+    }
+    // FP32 Kahan: one launch per band height present in the table
+    int begin = 0;
+    for (int b = 0; b < 3; ++b) {
+        const int end = L.band_end[b];
+        if (end <= begin) continue;
+        R.unit_base = begin;
+        R.total_units = end;
+        const dim3 g = grid(end - begin), blk(BT);
+        switch (b * 2 + L.law) {
+        case 0: hipLaunchKernelGGL(k_force_sym<1>, g, blk, 0, s, R); break;
+        case 1: hipLaunchKernelGGL(k_force_sym_paper<1>, g, blk, 0, s, R); break;
+        case 2: hipLaunchKernelGGL(k_force_sym<2>, g, blk, 0, s, R); break;
+        case 3: hipLaunchKernelGGL(k_force_sym_paper<2>, g, blk, 0, s, R); break;
+        case 4: hipLaunchKernelGGL(k_force_sym<4>, g, blk, 0, s, R); break;
+        default: hipLaunchKernelGGL(k_force_sym_paper<4>, g, blk, 0, s, R); break;
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        begin = end;
+    }
+    return begin == L.total_units ? hipSuccess : hipErrorInvalidValue;
 }
 
 hipError_t launch_combine(const Launch &L, int mode, hipStream_t s)
@@ -1744,13 +1583,11 @@ hipError_t launch_combine(const Launch &L, int mode, hipStream_t s)
     if (L.total_tunits == 0) return hipSuccess;
     const dim3 g(grid_for(L.total_tunits)), b(BT);
     if (mode == 0) {
-        hipLaunchKernelGGL((k_combine<float, false>), g, b, 0, s, L);
+        hipLaunchKernelGGL(k_combine_f32, g, b, 0, s, L);
     } else if (mode == 1) {
-        hipLaunchKernelGGL(k_combine_sym<NB_COMBINE_SEGS>, g, dim3(BT * NB_COMBINE_SEGS), 0, s, L);
-    } else if (FP64_SYM) {
-        hipLaunchKernelGGL(k_combine_sym64, g, b, 0, s, L);
+        hipLaunchKernelGGL(k_combine_sym, g, b, 0, s, L);
     } else {
-        hipLaunchKernelGGL((k_combine<double, false>), g, b, 0, s, L);
+        hipLaunchKernelGGL(k_combine_sym64, g, b, 0, s, L);
     }
     return hipGetLastError();
 }

@@ -48,12 +48,13 @@ struct TileCfg {
     int ki, nsplit, iblock, jchunk, n_iblocks, n_units, n_ounits;
     int npad, p1, nalloc, ntiles;
     int sym, ch;            // symmetric kernel (Kahan and FP64 modes) and its tiles per chunk
+    int rows;               // tile rows per band of the symmetric kernel (1, 2 or 4)
     size_t react_floats;    // reaction partials of the symmetric kernel (elements of the mode's type)
 };
 
 struct Override {
     int64_t lo, hi;
-    int nsplit;
+    int mode, law, nsplit, rows;
 };
 
 std::mutex g_cfg_mu;
@@ -61,12 +62,13 @@ std::vector<Override> g_overrides;
 
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
-// Sorted layout and work split of a system; a function of (n, n1, mode) and the overrides only.
-TileCfg tile_config(int64_t n, int64_t n1, int mode)
+// Sorted layout and work split of a system; a function of (n, n1, mode, law) and the overrides
+// only.
+TileCfg tile_config(int64_t n, int64_t n1, int mode, int law)
 {
     TileCfg c{};
-    c.ki = mode == NB_FP64 ? KI64 : KI32;
-    c.iblock = BT * c.ki;
+    c.ki = 1;
+    c.iblock = BT;
     c.p1 = (int)round_up(n1, TJ);
     c.npad = c.p1 + (int)round_up(n - n1, TJ);
     c.ntiles = c.npad / TJ;
@@ -74,27 +76,32 @@ TileCfg tile_config(int64_t n, int64_t n1, int mode)
     c.n_iblocks = c.npad > 0 ? c.nalloc / c.iblock : 0;
     c.n_ounits = (int)((n + BT - 1) / BT);
     int ns = 1;
+    c.rows = 1;
     if (mode != NB_FP32_PLAIN && c.ntiles > 0) {
-        // built-in rule: about 65536 work units, chunks of 2..16 tiles
+        // built-in rule: about 65536 work units, chunks of 2..16 tiles, one row per band
         const int64_t per = (int64_t)c.ntiles * c.n_iblocks / 65536;
         const int tpc = (int)std::min<int64_t>(16, std::max<int64_t>(2, per));
         ns = std::max(1, (c.ntiles + tpc / 2) / tpc);
         std::lock_guard<std::mutex> g(g_cfg_mu);
         for (const Override &o : g_overrides) {
-            if (n >= o.lo && n <= o.hi) ns = o.nsplit;
+            if (o.mode == mode && o.law == law && n >= o.lo && n <= o.hi) {
+                ns = o.nsplit;
+                c.rows = o.rows;
+            }
         }
     }
-    if ((mode == NB_FP32_KAHAN || (mode == NB_FP64 && FP64_SYM)) && c.ntiles > 0) {
-        // symmetric kernel: group g holds tile rows SYM_ROWS g .. SYM_ROWS g + SYM_ROWS - 1 and
-        // covers tiles SYM_ROWS g .. T-1 in chunks of ch tiles; its reactions are stored for the
-        // tiles after its first row. nsplit is the chunk count of the longest group.
+    if (mode != NB_FP32_KAHAN) c.rows = 1;  // bands of several rows: FP32 Kahan kernel only
+    if (mode != NB_FP32_PLAIN && c.ntiles > 0) {
+        // symmetric kernel: band g holds tile rows rows g .. rows g + rows - 1 and covers tiles
+        // rows g .. T-1 in chunks of ch tiles; its reactions are stored for the tiles after its
+        // first row. nsplit is the chunk count of the longest band.
         c.sym = 1;
         c.ch = std::max(1, (c.ntiles + std::max(ns, 1) - 1) / std::max(ns, 1));
         c.nsplit = (c.ntiles + c.ch - 1) / c.ch;
         c.jchunk = c.ch * TJ;
         int64_t units = 0, react_tiles = 0;
-        for (int g = 0; g * SYM_ROWS < c.ntiles; ++g) {
-            const int span = c.ntiles - g * SYM_ROWS;
+        for (int g = 0; g * c.rows < c.ntiles; ++g) {
+            const int span = c.ntiles - g * c.rows;
             units += (span + c.ch - 1) / c.ch;
             react_tiles += span - 1;
         }
@@ -358,6 +365,9 @@ int run_steps(const Launch &L, int mode, int n_steps, bool need_combine, hipStre
     return NB_OK;
 }
 
+// Index of a band height in Launch::band_end.
+int band_index(int rows) { return rows >= 4 ? 2 : (rows == 2 ? 1 : 0); }
+
 Launch single_launch(const nb_system *s)
 {
     Launch L{};
@@ -367,6 +377,8 @@ Launch single_launch(const nb_system *s)
     L.total_units = s->cfg.n_units;
     L.total_ounits = s->cfg.n_ounits;
     L.total_tunits = s->cfg.ntiles;
+    const int b = band_index(s->cfg.rows);
+    for (int k = 0; k < 3; ++k) L.band_end[k] = k >= b ? L.total_units : 0;
     return L;
 }
 
@@ -413,22 +425,47 @@ int check_system_list(nb_system *const *sys, int32_t n_sys)
     return NB_OK;
 }
 
+// Table order of a multi-system launch: by band height (so each height's force units are one
+// range), in the given order within a height. Writes n_sys indices into `order`. The order
+// decides only which workgroup runs which unit, never a system's arithmetic.
+void table_order(nb_system *const *sys, int32_t n_sys, int *order)
+{
+    int k = 0;
+    for (int b = 0; b < 3; ++b) {
+        for (int i = 0; i < n_sys; ++i) {
+            if (band_index(sys[i]->cfg.rows) == b) order[k++] = i;
+        }
+    }
+}
+
+// Prefix offsets of table entry `pos` (system s) and the launch totals after it.
+void table_append(Launch &L, const nb_system *s, int32_t &unit_begin, int32_t &ounit_begin,
+                  int32_t &tunit_begin)
+{
+    unit_begin = L.total_units;
+    ounit_begin = L.total_ounits;
+    tunit_begin = L.total_tunits;
+    L.total_units += s->cfg.n_units;
+    L.total_ounits += s->cfg.n_ounits;
+    L.total_tunits += s->cfg.ntiles;
+    const int b = band_index(s->cfg.rows);
+    for (int k = b; k < 3; ++k) L.band_end[k] = L.total_units;
+}
+
 // Segment table of several systems: each system's units follow the previous system's.
 Launch build_table(nb_system *const *sys, int32_t n_sys, std::vector<SysDesc> &table,
                    bool &combine)
 {
     table.resize(n_sys);
+    std::vector<int> order((size_t)n_sys);
+    table_order(sys, n_sys, order.data());
     Launch L{};
     combine = false;
     for (int k = 0; k < n_sys; ++k) {
-        table[k] = sys[k]->desc;
-        table[k].unit_begin = L.total_units;
-        table[k].ounit_begin = L.total_ounits;
-        table[k].tunit_begin = L.total_tunits;
-        L.total_units += sys[k]->cfg.n_units;
-        L.total_ounits += sys[k]->cfg.n_ounits;
-        L.total_tunits += sys[k]->cfg.ntiles;
-        combine = combine || sys[k]->cfg.nsplit > 1 || sys[k]->cfg.sym;
+        const nb_system *s = sys[order[k]];
+        table[k] = s->desc;
+        table_append(L, s, table[k].unit_begin, table[k].ounit_begin, table[k].tunit_begin);
+        combine = combine || s->cfg.nsplit > 1 || s->cfg.sym;
     }
     L.n_sys = n_sys;
     L.law = sys[0]->p.law;
@@ -456,6 +493,7 @@ void fill_desc(SysDesc &d, const nb_params *p, const nb_buffers *b, const TileCf
     d.react = cfg.sym ? reinterpret_cast<float *>(base + lay.react) : nullptr;
     d.ch = cfg.ch;
     d.sym = cfg.sym;
+    d.rows = cfg.rows;
     d.xs = base + lay.xs;
     d.ys = base + lay.ys;
     d.zs = base + lay.zs;
@@ -533,7 +571,7 @@ void fill_state(DevState &init, const nb_params *p)
 
 extern "C" {
 
-int nb_version(void) { return 3; }
+int nb_version(void) { return 4; }
 
 const char *nb_strerror(int status)
 {
@@ -549,16 +587,18 @@ const char *nb_strerror(int status)
     }
 }
 
-int nb_tile_config(int64_t n, int64_t n1, int32_t mode, int32_t *ki, int32_t *nsplit,
-                   int32_t *iblock, int32_t *jchunk)
+int nb_tile_config(int64_t n, int64_t n1, int32_t mode, int32_t law, int32_t *ki, int32_t *nsplit,
+                   int32_t *iblock, int32_t *jchunk, int32_t *rows)
 {
     if (n < 0 || n >= (int64_t(1) << 30) || n1 < 0 || n1 > n) return NB_E_INVAL;
     if (mode != NB_FP32_PLAIN && mode != NB_FP32_KAHAN && mode != NB_FP64) return NB_E_INVAL;
-    TileCfg c = tile_config(n, n1, mode);
+    if (law != NB_LAW_CONTACT && law != NB_LAW_PAPER) return NB_E_INVAL;
+    TileCfg c = tile_config(n, n1, mode, law);
     if (ki) *ki = c.ki;
     if (nsplit) *nsplit = c.nsplit;
     if (iblock) *iblock = c.iblock;
     if (jchunk) *jchunk = c.jchunk;
+    if (rows) *rows = c.rows;
     return NB_OK;
 }
 
@@ -569,21 +609,29 @@ int nb_set_force_grid(int32_t blocks)
     return NB_OK;
 }
 
-int nb_tile_override(int64_t n_lo, int64_t n_hi, int32_t nsplit)
+int nb_tile_override(int64_t n_lo, int64_t n_hi, int32_t mode, int32_t law, int32_t nsplit,
+                     int32_t rows)
 {
     if (n_lo < 0 || n_hi < n_lo || nsplit < 0 || nsplit > 4096) return NB_E_INVAL;
+    if (mode != NB_FP32_PLAIN && mode != NB_FP32_KAHAN && mode != NB_FP64) return NB_E_INVAL;
+    if (law != NB_LAW_CONTACT && law != NB_LAW_PAPER) return NB_E_INVAL;
+    if (nsplit > 0 && rows != 1 && rows != 2 && rows != 4) return NB_E_INVAL;
+    if (nsplit > 0 && rows != 1 && mode != NB_FP32_KAHAN) return NB_E_INVAL;
     std::lock_guard<std::mutex> g(g_cfg_mu);
     g_overrides.erase(std::remove_if(g_overrides.begin(), g_overrides.end(),
-                                     [&](const Override &o) { return o.lo == n_lo && o.hi == n_hi; }),
+                                     [&](const Override &o) {
+                                         return o.mode == mode && o.law == law && o.lo == n_lo &&
+                                                o.hi == n_hi;
+                                     }),
                       g_overrides.end());
-    if (nsplit > 0) g_overrides.push_back({n_lo, n_hi, nsplit});
+    if (nsplit > 0) g_overrides.push_back({n_lo, n_hi, mode, law, nsplit, rows});
     return NB_OK;
 }
 
 int nb_scratch_bytes(const nb_params *p, size_t *out)
 {
     if (!params_ok(p) || !out) return NB_E_INVAL;
-    TileCfg c = tile_config(p->n, p->n1, p->mode);
+    TileCfg c = tile_config(p->n, p->n1, p->mode, p->law);
     if (c.n_units < 0) return NB_E_NOMEM;
     *out = layout_for(p->mode, p->law, c).total;
     return NB_OK;
@@ -603,7 +651,7 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
         if (!b->side) return NB_E_INVAL;
     }
     if (!b->scratch || !aligned(b->scratch, ALIGN)) return NB_E_INVAL;
-    TileCfg cfg = tile_config(p->n, p->n1, p->mode);
+    TileCfg cfg = tile_config(p->n, p->n1, p->mode, p->law);
     if (cfg.n_units < 0) return NB_E_NOMEM;
     Layout lay = layout_for(p->mode, p->law, cfg);
     if (b->scratch_bytes < lay.total) return NB_E_NOMEM;
@@ -668,11 +716,10 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
                            hipMemcpyHostToDevice, st) != hipSuccess) { rc = NB_E_HIP; break; }
         std::vector<int32_t> units;
         if (cfg.sym) {
-            // (row group, chunk) pairs, full-length chunks first (each group's last chunk may be
-            // short)
+            // (band, chunk) pairs, full-length chunks first (each band's last chunk may be short)
             std::vector<std::pair<int, std::pair<int, int>>> order;
-            for (int g = 0; g * SYM_ROWS < cfg.ntiles; ++g) {
-                const int span = cfg.ntiles - g * SYM_ROWS;
+            for (int g = 0; g * cfg.rows < cfg.ntiles; ++g) {
+                const int span = cfg.ntiles - g * cfg.rows;
                 const int chunks = (span + cfg.ch - 1) / cfg.ch;
                 for (int c = 0; c < chunks; ++c) {
                     const int len = std::min(cfg.ch, span - c * cfg.ch);
@@ -807,20 +854,17 @@ int nb_step_static(nb_system *const *sys, int32_t n_sys, int32_t n_steps, void *
     L.n_sys = n_sys;
     L.law = sys[0]->p.law;
     bool combine = false;
+    int order[NB_STATIC_MAX_SYS];
+    table_order(sys, n_sys, order);
     TableChunk c;
     for (int first = 0; first < n_sys; first += TABLE_CHUNK) {
         std::memset(&c, 0, sizeof c);
         c.first = first;
         c.count = std::min(TABLE_CHUNK, n_sys - first);
         for (int k = 0; k < c.count; ++k) {
-            const nb_system *s = sys[first + k];
+            const nb_system *s = sys[order[first + k]];
             c.src[k] = s->d_desc;
-            c.unit_begin[k] = L.total_units;
-            c.ounit_begin[k] = L.total_ounits;
-            c.tunit_begin[k] = L.total_tunits;
-            L.total_units += s->cfg.n_units;
-            L.total_ounits += s->cfg.n_ounits;
-            L.total_tunits += s->cfg.ntiles;
+            table_append(L, s, c.unit_begin[k], c.ounit_begin[k], c.tunit_begin[k]);
             combine = combine || s->cfg.nsplit > 1 || s->cfg.sym;
         }
         NB_TRY(launch_copy_table(table, c, st));
@@ -990,7 +1034,7 @@ int nb_l1_log(nb_system *s, int32_t *out_host, int32_t max_steps, int32_t *n_out
 int nb_valu_probe(int32_t op, int32_t blocks, int32_t iters, void *sink, void *stream,
                   double *ms, int64_t *lane_ops)
 {
-    if (op < 0 || op > 3 || blocks < 1 || iters < 1 || !sink || !ms || !lane_ops)
+    if (op < 0 || op > 7 || blocks < 1 || iters < 1 || !sink || !ms || !lane_ops)
         return NB_E_INVAL;
     int device = -1;
     NB_TRY(hipGetDevice(&device));

@@ -36,9 +36,9 @@ int main(void)
     p.mode = NB_FP32_PLAIN;
     rc = nb_scratch_bytes(&p, &bytes);
     printf("plain-paper %d %s\n", rc, nb_strerror(rc));
-    int32_t ki = 0, ns = 0, ib = 0, jc = 0;
-    rc = nb_tile_config(262144, 201650, NB_FP32_KAHAN, &ki, &ns, &ib, &jc);
-    printf("tile %d %d %d %d %d\n", rc, ki, ns, ib, jc);
+    int32_t ki = 0, ns = 0, ib = 0, jc = 0, rows = 0;
+    rc = nb_tile_config(262144, 201650, NB_FP32_KAHAN, NB_LAW_CONTACT, &ki, &ns, &ib, &jc, &rows);
+    printf("tile %d %d %d %d %d %d\n", rc, ki, ns, ib, jc, rows);
     printf("version %d\n", nb_version());
     nb_system *s = NULL;
     rc = nb_create(NULL, NULL, NULL, &s);

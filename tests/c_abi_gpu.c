@@ -1,7 +1,8 @@
 /* A whole run through the C ABI from C, with device memory from hipMalloc and no PyTorch:
  * reads a two-star state (n, n1, params, then x y z vx vy vz as float arrays) from argv[1],
  * steps it argv[3] times in FP32 Kahan mode with the split request argv[4] (0 = the built-in
- * rule; see nb_tile_override) and writes the final positions and velocities and the diagnostics
+ * rule; see nb_tile_override) and band height argv[5], and writes the final positions and
+ * velocities and the diagnostics
  * to argv[2]. Test infrastructure for tests/test_gpu_c_abi.py. */
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
@@ -22,7 +23,7 @@
 
 int main(int argc, char **argv)
 {
-    if (argc != 5) return 2;
+    if (argc != 6) return 2;
     FILE *f = fopen(argv[1], "rb");
     if (!f) return 2;
     int64_t hdr[2];
@@ -51,7 +52,7 @@ int main(int argc, char **argv)
     p.mode = NB_FP32_KAHAN;
     p.law = NB_LAW_CONTACT;
 
-    CHECK(nb_tile_override(n, n, atoi(argv[4])));
+    CHECK(nb_tile_override(n, n, NB_FP32_KAHAN, NB_LAW_CONTACT, atoi(argv[4]), atoi(argv[5])));
     size_t scratch_bytes = 0;
     CHECK(nb_scratch_bytes(&p, &scratch_bytes));
     void *arr[9];

@@ -82,11 +82,37 @@ def test_tile_config_covers_every_slot(nb, mode, n, n1):
 
 
 def test_tile_override(nb):
-    before = nb.nb_tile_config(100000, 60000, nb.NB_FP32_KAHAN)["nsplit"]
-    nb.nb_tile_override(99000, 101000, 3)
-    assert nb.nb_tile_config(100000, 60000, nb.NB_FP32_KAHAN)["nsplit"] == 3
-    nb.nb_tile_override(99000, 101000, 0)
-    assert nb.nb_tile_config(100000, 60000, nb.NB_FP32_KAHAN)["nsplit"] == before
+    K, F = nb.NB_FP32_KAHAN, nb.NB_FP64
+    before = nb.nb_tile_config(100000, 60000, K)  # the installed table's choice, if any
+    before64 = nb.nb_tile_config(100000, 60000, F)
+    nb.nb_tile_override(99000, 101000, K, 3, 2)
+    cfg = nb.nb_tile_config(100000, 60000, K)
+    assert cfg["nsplit"] == 3 and cfg["rows"] == 2
+    # overrides are per mode: the FP64 split is untouched
+    assert nb.nb_tile_config(100000, 60000, F) == before64
+    nb.nb_tile_override(99000, 101000, F, 5, 1)
+    assert nb.nb_tile_config(100000, 60000, F)["nsplit"] == 5
+    assert nb.nb_tile_config(100000, 60000, K)["nsplit"] == 3
+    # and per element law: the eqs. (4)-(6) split of the same size is untouched
+    P = nb.NB_LAW_PAPER
+    before_p = nb.nb_tile_config(100000, 60000, K, P)
+    nb.nb_tile_override(99000, 101000, K, 7, 1, law=P)
+    assert nb.nb_tile_config(100000, 60000, K, P)["nsplit"] == 7
+    assert nb.nb_tile_config(100000, 60000, K)["nsplit"] == 3
+    nb.nb_tile_override(99000, 101000, K, 0, 1)
+    nb.nb_tile_override(99000, 101000, F, 0, 1)
+    nb.nb_tile_override(99000, 101000, K, 0, 1, law=P)
+    assert nb.nb_tile_config(100000, 60000, K) == before
+    assert nb.nb_tile_config(100000, 60000, F) == before64
+    assert nb.nb_tile_config(100000, 60000, K, P) == before_p
+
+
+# (n_lo, n_hi, mode, law, nsplit, rows)
+@pytest.mark.parametrize("args", [(0, 10, 1, 0, 3, 3), (0, 10, 2, 0, 3, 2), (0, 10, 0, 0, 3, 4),
+                                  (0, 10, 7, 0, 3, 1), (10, 0, 1, 0, 3, 1), (0, 10, 1, 0, -1, 1),
+                                  (0, 10, 1, 2, 3, 1)])
+def test_tile_override_rejects_bad_arguments(nb, args):
+    assert nb.load().nb_tile_override(*args) == nb.NB_E_INVAL
 
 
 @pytest.mark.parametrize("bad", [dict(n=-1), dict(n1=3000), dict(mode=7), dict(D1=0.0),
@@ -165,22 +191,31 @@ def test_retention_rejects_null_arguments(nb):
 
 
 def test_scratch_bytes_grow_by_sorted_velocities_under_the_paper_law(nb):
-    """NB_LAW_PAPER adds three sorted velocity arrays (nalloc slots each, 256-byte aligned). The
-    system is large enough that neither law splits its work units by j group (small systems
-    under the contact law hold four times the chunk partials)."""
+    """NB_LAW_PAPER adds three sorted velocity arrays (nalloc slots each, 256-byte aligned) to a
+    system of the same work split."""
     big = dict(n=200000, n1=150000)
-    base = _params(nb, **big)
-    paper = _params(nb, law=nb.NB_LAW_PAPER, eps=0.001, gamma=1.0, beta=0.5, **big)
-    extra = nb.nb_scratch_bytes(paper) - nb.nb_scratch_bytes(base)
+    # the same work split for both laws (a tuned table may give them different ones)
+    splits = [(m, w) for m in (nb.NB_FP32_KAHAN, nb.NB_FP64)
+              for w in (nb.NB_LAW_CONTACT, nb.NB_LAW_PAPER)]
+    for m, w in splits:
+        nb.nb_tile_override(big["n"], big["n"], m, 40, 1, law=w)
+    try:
+        base = _params(nb, **big)
+        paper = _params(nb, law=nb.NB_LAW_PAPER, eps=0.001, gamma=1.0, beta=0.5, **big)
+        extra = nb.nb_scratch_bytes(paper) - nb.nb_scratch_bytes(base)
+        b64 = _params(nb, mode=nb.NB_FP64, **big)
+        p64 = _params(nb, mode=nb.NB_FP64, law=nb.NB_LAW_PAPER, eps=0.001, gamma=1.0, beta=0.5,
+                      **big)
+        extra64 = nb.nb_scratch_bytes(p64) - nb.nb_scratch_bytes(b64)
+    finally:
+        for m, w in splits:
+            nb.nb_tile_override(big["n"], big["n"], m, 0, 1, law=w)
     # each star padded to whole 256-slot tiles (a multiple of the i-block, so nalloc = slots)
     slots = -(-(base.n1) // 256) * 256 + -(-(base.n - base.n1) // 256) * 256
     per = -(-slots * 4 // 256) * 256
     assert extra == 3 * per
     # FP64: eight bytes per slot
-    b64 = _params(nb, mode=nb.NB_FP64, **big)
-    p64 = _params(nb, mode=nb.NB_FP64, law=nb.NB_LAW_PAPER, eps=0.001, gamma=1.0, beta=0.5,
-                  **big)
-    assert nb.nb_scratch_bytes(p64) - nb.nb_scratch_bytes(b64) == 3 * (-(-slots * 8 // 256) * 256)
+    assert extra64 == 3 * (-(-slots * 8 // 256) * 256)
 
 
 def test_huge_systems_report_nomem_instead_of_overflowing(nb):

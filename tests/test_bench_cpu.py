@@ -23,10 +23,12 @@ def test_counter_record_requires_matching_source_and_split():
     with open(bench.COUNTERS_FILE) as f:
         rec = json.load(f)
     entry = rec["c3:kahan"]
+    cfg = {"nsplit": entry["nsplit"], "rows": entry.get("rows", 1)}
     if entry["kernel_sha"] == bench.kernel_source_sha():
-        assert bench.counter_record("c3", "kahan", entry["nsplit"]) == entry
-    assert bench.counter_record("c3", "kahan", entry["nsplit"] + 1) is None
-    assert bench.counter_record("c3", "nonexistent-mode", entry["nsplit"]) is None
+        assert bench.counter_record("c3", "kahan", cfg) == entry
+    assert bench.counter_record("c3", "kahan", dict(cfg, nsplit=cfg["nsplit"] + 1)) is None
+    assert bench.counter_record("c3", "kahan", dict(cfg, rows=3)) is None
+    assert bench.counter_record("c3", "nonexistent-mode", cfg) is None
 
 
 def test_served_sample_takes_one_request_per_size_decile():

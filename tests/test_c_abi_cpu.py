@@ -43,6 +43,7 @@ def test_errors_from_c(c_output):
 
 
 def test_tile_config_and_version_from_c(c_output):
-    rc, ki, ns, ib, jc = (int(x) for x in c_output["tile"].split())
+    rc, ki, ns, ib, jc, rows = (int(x) for x in c_output["tile"].split())
     assert rc == 0 and ki == 1 and ib == 256 and ns >= 1 and jc % 256 == 0
-    assert int(c_output["version"]) >= 3
+    assert rows in (1, 2, 4)
+    assert int(c_output["version"]) >= 4

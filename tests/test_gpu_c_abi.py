@@ -36,11 +36,16 @@ def test_c_program_matches_python_binding(tmp_path):
     # the binding installs the tuned split table when it loads; the C program asks for the same
     from paper_2303_12166_amd import autotune
 
-    table = autotune.load_table(autotune.TABLE_PATH) or {"buckets": []}
-    req = next((b["nsplit"] for b in table["buckets"] if b["n_lo"] <= ic.n <= b["n_hi"]), 0)
-    print_case("C program", ic.n, steps, "split request", req)
-    r = subprocess.run([EXE, str(src), str(out), str(steps), str(req)], capture_output=True,
-                       text=True, timeout=120)
+    table = autotune.load_table(autotune.TABLE_PATH) or {}
+    if table.get("library_version") != nb.nb_version():
+        table = {}
+    buckets = table.get("tables", {}).get("kahan", {}).get("buckets", [])
+    b = next((b for b in buckets if b["n_lo"] <= ic.n <= b["n_hi"]), {"nsplit": 0, "rows": 1})
+    req, rows = b["nsplit"], b.get("rows", 1)
+    assert nb.nb_tile_config(ic.n, ic.n1, nb.NB_FP32_KAHAN)["rows"] == rows
+    print_case("C program", ic.n, steps, "split request", req, "rows", rows)
+    r = subprocess.run([EXE, str(src), str(out), str(steps), str(req), str(rows)],
+                       capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr
     raw = np.fromfile(out, dtype=np.float32, count=6 * ic.n)
     tail = np.fromfile(out, dtype=np.float64, offset=6 * ic.n * 4)

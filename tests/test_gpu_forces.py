@@ -134,20 +134,23 @@ def test_repeated_evaluation_is_bitwise_stable():
     s.close()
 
 
-@pytest.mark.parametrize("mode,tol", [("kahan", 1e-5), ("fp64", 1e-12)])
+@pytest.mark.parametrize("mode,rows,tol", [("kahan", 1, 1e-5), ("kahan", 2, 1e-5),
+                                           ("kahan", 4, 1e-5), ("fp64", 1, 1e-12)])
 @pytest.mark.parametrize("nsplit", [1, 2, 3, 7])
-def test_j_split_choices_agree(nsplit, mode, tol):
-    """Every chunking of the symmetric kernels (FP32 Kahan and FP64) gives oracle parity."""
+def test_j_split_choices_agree(nsplit, mode, rows, tol):
+    """Every chunking and band height of the symmetric kernels (FP32 Kahan and FP64) gives
+    oracle parity."""
     nb = require_gpu()
     n = 12345
     ic = synth.make_binary(n, 0.6, seed=2)
-    nb.nb_tile_override(n, n, nsplit)
+    nb.nb_tile_override(n, n, nb.MODES[mode], nsplit, rows)
     try:
         cfg = nb.nb_tile_config(n, ic.n1, nb.MODES[mode])
+        assert cfg["rows"] == rows
         print_case("nsplit", nsplit, mode, cfg)
         a = _gpu_forces(nb, ic, mode)
     finally:
-        nb.nb_tile_override(n, n, 0)
+        nb.nb_tile_override(n, n, nb.MODES[mode], 0, 1)
     ref = oracle.accel(_oracle_input(ic, mode), ic.n1, ic.G, ic.m, ic.D1, ic.D2)
     assert force_error(a, ref) <= tol
 
