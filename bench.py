@@ -205,6 +205,42 @@ def valu_probe() -> dict:
     return out
 
 
+def issue_model(counters: dict, probe: dict, rows: int, pairs: float, avg_s: float):
+    """Issue-time estimates of the force kernel from its instruction counts per pair (rocprofv3
+    counters by class) and the probe's measured single-stream rate of each class on this part.
+
+    serial_ms: every instruction at its class's rate, one after the other (rotated DPP
+    subtractions, 3 per pair and band of `rows` rows, at the probe's back-to-back DPP rate);
+    mul_trans_ms: the multiplies, FMAs, transcendentals and other non-add VALU instructions
+    alone, that is every add, subtraction and DPP subtraction issued beside them at no cost.
+    A kernel that overlaps the classes runs below serial_ms; mul_trans_ms is a floor only as far
+    as the multiply and transcendental streams do not overlap each other."""
+    need = ("add_f32_lane_instructions_per_pair", "mul_f32_lane_instructions_per_pair",
+            "fma_f32_lane_instructions_per_pair", "trans_lane_instructions_per_pair",
+            "valu_lane_instructions_per_pair")
+    rkeys = ("v_add_f32", "v_mul_f32", "v_rsq_f32", "v_sub_f32 (DPP wave_ror:1 source)")
+    if not probe or avg_s <= 0 or any(counters.get(k) is None for k in need) or \
+            any(not probe.get(k) for k in rkeys):
+        return None
+    add_all = counters["add_f32_lane_instructions_per_pair"]
+    dpp = 3.0 / rows if rows else 0.0
+    add = max(add_all - dpp, 0.0)
+    mul = counters["mul_f32_lane_instructions_per_pair"] + counters[
+        "fma_f32_lane_instructions_per_pair"]
+    trans = counters["trans_lane_instructions_per_pair"]
+    other = max(counters["valu_lane_instructions_per_pair"] - add_all - mul - trans, 0.0)
+    r_add, r_mul, r_trans, r_dpp = (probe[k] for k in rkeys)
+    # CU-clocks per pair; other VALU (integer, moves, selects) priced like a multiply
+    heavy = (mul + other) / r_mul + trans / r_trans
+    serial = add / r_add + dpp / r_dpp + heavy
+    scale = pairs / (N_CU * CLOCK_HZ)
+    return {"per_pair": {"add": round(add, 3), "dpp_sub": round(dpp, 3), "mul_fma": round(mul, 3),
+                         "trans": round(trans, 3), "other": round(other, 3)},
+            "serial_ms": round(serial * scale * 1e3, 3),
+            "mul_trans_ms": round(heavy * scale * 1e3, 3),
+            "measured_ms": round(avg_s * 1e3, 3)}
+
+
 def copy_calibration() -> int:
     import torch
 
@@ -363,9 +399,86 @@ def precision_study(steps: int) -> dict:
     return out
 
 
-def lobe_fill(extra_steps: int, n: int = 65536, q: float = 0.5, bin_steps: int = 100) -> dict:
+def morton_perm(pos, n1: int):
+    """A sorted order like the library's creation-time one, for the given positions: each star
+    in Morton order of 10-bit coordinates inside its own bounding box (ties by index), star 2
+    from slot roundup(n1, 256), padding -1."""
+    import numpy as np
+
+    def spread(v):
+        v = v.astype(np.uint32) & 0x3FF
+        v = (v | (v << 16)) & 0x030000FF
+        v = (v | (v << 8)) & 0x0300F00F
+        v = (v | (v << 4)) & 0x030C30C3
+        v = (v | (v << 2)) & 0x09249249
+        return v
+
+    def order(b, e):
+        p = pos[b:e].astype(np.float64)
+        if p.shape[0] == 0:
+            return np.zeros(0, dtype=np.int32)
+        lo, hi = p.min(axis=0), p.max(axis=0)
+        span = np.where(hi > lo, hi - lo, 1.0)
+        q = np.minimum(1023.0, np.clip((p - lo) / span, 0.0, 1.0) * 1024.0).astype(np.uint32)
+        key = spread(q[:, 0]) | (spread(q[:, 1]) << 1) | (spread(q[:, 2]) << 2)
+        return (b + np.lexsort((np.arange(e - b), key))).astype(np.int32)
+
+    n = pos.shape[0]
+    p1 = -(-n1 // 256) * 256
+    slots = p1 + -(-(n - n1) // 256) * 256
+    perm = np.full(slots, -1, dtype=np.int32)
+    perm[:n1] = order(0, n1)
+    perm[p1:p1 + n - n1] = order(n1, n)
+    return perm
+
+
+def near_share(nb, s, n1: int, D1: float, D2: float, fresh: bool = False) -> float:
+    """Share of the (64-element i block, later j tile) pairs of the symmetric kernel that the
+    bounding-box test leaves on the near (contact-law) path, for the system's current positions
+    in its sorted order (fresh=False: the library's, fixed when the system was created;
+    fresh=True: a Morton order of the current positions, what a re-sort would give)."""
+    import numpy as np
+
+    pos = s.positions()
+    perm = morton_perm(pos, n1) if fresh else nb.nb_sorted_order(s.handle, s.stream)
+    slots = perm.size
+    T = slots // 256
+    P = np.full((slots, 3), np.nan)
+    ok = perm >= 0
+    P[ok] = pos[perm[ok]]
+    tiles = P.reshape(T, 256, 3)
+    waves = P.reshape(T * 4, 64, 3)
+    with np.errstate(all="ignore"):
+        import warnings
+
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore", RuntimeWarning)
+            tlo, thi = np.nanmin(tiles, axis=1), np.nanmax(tiles, axis=1)
+            wlo, whi = np.nanmin(waves, axis=1), np.nanmax(waves, axis=1)
+    p1 = -(-n1 // 256) * 256
+    tstar = (np.arange(T) * 256 >= p1).astype(int)
+    Ds = np.array([D1, 0.5 * (D1 + D2), D2])
+    far2 = Ds * Ds * (1.0 + 2.0e-5)
+    near = total = 0
+    for w in range(T * 4):
+        I = w // 4
+        J = np.arange(I + 1, T)
+        if J.size == 0 or np.isnan(wlo[w]).any():
+            continue
+        gap = np.maximum(0.0, np.maximum(tlo[J] - whi[w], wlo[w] - thi[J]))
+        gap2 = np.nansum(gap * gap, axis=1)
+        cls = tstar[I] + tstar[J]
+        valid = ~np.isnan(tlo[J]).any(axis=1)
+        near += int(np.count_nonzero((gap2 < far2[cls]) & valid))
+        total += int(np.count_nonzero(valid))
+    return near / max(total, 1)
+
+
+def lobe_fill(extra_steps: int, n: int = 65536, q: float = 0.5, bin_steps: int = 100,
+              resort_every: int = 0) -> dict:
     """Grow the donor to its Roche lobe and past the stop; record the per-step L1 flux series
-    and, every 500 steps, the accretor-side retention of the transferred elements."""
+    and, every 500 steps, the accretor-side retention of the transferred elements. With
+    resort_every = K (a multiple of 500), the sorted order is rebuilt every K steps."""
     import math
 
     import numpy as np
@@ -376,17 +489,29 @@ def lobe_fill(extra_steps: int, n: int = 65536, q: float = 0.5, bin_steps: int =
 
     ic = synth.make_binary(n, q, seed=0)
     s = nb.System.from_ic(ic, mode="kahan")
-    rows, ret = [], []
+    def shares(D2):
+        return {"near_share": near_share(nb, s, ic.n1, ic.D1, D2),
+                "near_share_fresh_order": near_share(nb, s, ic.n1, ic.D1, D2, fresh=True)}
+
+    rows, ret, near = [], [], [dict(step=0, **shares(ic.D2))]
+    chunk_ms = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done, stop_seen = 0, None
     while stop_seen is None or done < stop_seen + extra_steps:
         k = 500 if stop_seen is None else min(500, stop_seen + extra_steps - done)
+        tc = time.perf_counter()
         s.step(k)
+        s.synchronize()
+        chunk_ms.append([done + k, round((time.perf_counter() - tc) / k * 1e3, 4)])
         done += k
         rows.append(s.l1_log(k))
         ret.append({"step": done, "n_past_bound": list(s.retention())})
         d = s.diagnostics()
+        if resort_every and done % resort_every == 0:
+            s.resort()
+        if done % 2000 == 0:
+            near.append(dict(step=done, **shares(d["D2"])))
         if stop_seen is None and d["growth_stopped"]:
             stop_seen = done
         log("lobe fill: %d steps, past L1 %d, growth %s" % (done, rows[-1][-1, 1],
@@ -396,6 +521,7 @@ def lobe_fill(extra_steps: int, n: int = 65536, q: float = 0.5, bin_steps: int =
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     d = s.diagnostics()
+    near.append(dict(step=done, **shares(d["D2"])))
     s.close()
     series = np.concatenate(rows)
     assert list(series[:, 0]) == list(range(1, done + 1))
@@ -407,7 +533,10 @@ def lobe_fill(extra_steps: int, n: int = 65536, q: float = 0.5, bin_steps: int =
     return {
         "workload": "two-star binary, N=%d, q=%g, FP32 Kahan, dt=1e-4, donor element diameter "
                     "grown by 1e-4 per step from R2_0 = %.2f until the nominal radius passes "
-                    "r_L a (eq. 3), then %d more steps" % (n, q, ic.R2, extra_steps),
+                    "r_L a (eq. 3), then %d more steps%s" % (
+                        n, q, ic.R2, extra_steps,
+                        ", sorted order rebuilt every %d steps" % resort_every if resort_every
+                        else ""),
         "steps": done,
         "growth_stopped": d["growth_stopped"],
         "growth_steps": int(round(math.log(d["D2"] / ic.D2) / math.log(1.0 + 1e-4))),
@@ -420,6 +549,10 @@ def lobe_fill(extra_steps: int, n: int = 65536, q: float = 0.5, bin_steps: int =
                  "rows": bins},
         "retention": ret,
         "ms_per_step": t / done * 1e3,
+        # step time of each 500-step stretch (host-timed, the read-backs between stretches
+        # excluded) and the near-path share of the sorted order over the run
+        "ms_per_step_by_stretch": chunk_ms,
+        "near_share": near,
     }
 
 
@@ -453,6 +586,9 @@ def main() -> int:
                          "accretor-side retention")
     ap.add_argument("--lobe-n", type=int, default=65536, help="elements of the --lobe-fill run")
     ap.add_argument("--lobe-q", type=float, default=0.5, help="mass ratio of the --lobe-fill run")
+    ap.add_argument("--resort-every", type=int, default=0,
+                    help="--lobe-fill: rebuild the sorted order every this many steps (multiple "
+                         "of 500; 0 never)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (three times), the reference "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -477,7 +613,10 @@ def main() -> int:
 
         nb.load()
         torch.cuda.set_device(0)
-        res = lobe_fill(2000 if args.steps is None else args.steps, n=args.lobe_n, q=args.lobe_q)
+        if args.resort_every % 500:
+            ap.error("--resort-every must be a multiple of 500")
+        res = lobe_fill(2000 if args.steps is None else args.steps, n=args.lobe_n, q=args.lobe_q,
+                        resort_every=args.resort_every)
         print(json.dumps({"metric": "lobe-filling run: L1 flux series and retention",
                           "value": None, "n_gpus": 1, "data": "synthetic", "lobe_fill": res}),
               flush=True)
@@ -611,6 +750,11 @@ def main() -> int:
             if probe and probe.get("v_fma_f32"):
                 roofline["counters"]["valu_issue_frac_of_probe_fma"] = round(
                     rate / (N_CU * CLOCK_HZ) / probe["v_fma_f32"], 4)
+            model = issue_model(counters, probe, cfg["rows"] if kernel.startswith("k_force_sym<")
+                                or kernel.startswith("k_force_sym_paper<") else 0,
+                                evaluated, avg_s)
+            if model:
+                roofline["counters"]["issue_model"] = model
 
     out = {
         "metric": METRIC,

@@ -212,6 +212,25 @@ int nb_l1_log(nb_system *s, int32_t *out_host, int32_t max_steps, int32_t *n_out
  * Returns NB_E_INVAL for null arguments. */
 int nb_retention(nb_system *s, int32_t *n_past, int32_t *n_bound, void *stream);
 
+/* Rebuilds the sorted order the force kernels work in from the current positions (each star in
+ * Morton order, as nb_create does from the initial ones). Elements drift from their creation-time
+ * neighbours as a run goes on and the donor grows; tiles then span more space, more of them need
+ * the contact test, and the force evaluation slows. The new order changes the order of the pair
+ * sums, so results agree with an unsorted run to rounding, not bitwise; a system re-sorted by a
+ * rule that depends only on its own state (for example every K of its own steps) gets the same
+ * bits alone and in any batch. Synchronises `stream` (the positions are read back and sorted on
+ * the host); work on the system must be ordered before the call. NB_E_INVAL for a null or
+ * foreign system. */
+int nb_resort(nb_system *s, void *stream);
+
+/* The sorted order the force kernels work in (a diagnostic of the layout, no part of the model):
+ * slot k of the sorted copy holds element out_host[k], or -1 for a padding slot. Star 1 fills
+ * slots [0, n1) in Morton order of its positions at nb_create, star 2 starts at slot
+ * roundup(n1, 256), each star padded to whole tiles of 256 slots. Copies min(cap, total) entries
+ * (int32) and sets *n_out to the total slot count. Synchronises `stream`. NB_E_INVAL for null
+ * arguments, a negative cap or a foreign system. */
+int nb_sorted_order(nb_system *s, int32_t *out_host, int64_t cap, int64_t *n_out, void *stream);
+
 /* Force-kernel timing: while enabled, every force launch issued by nb_forces/nb_step is
  * bracketed by HIP events on its stream. nb_timing_read synchronises those events and returns
  * the summed kernel time (ms) and launch count since the last reset. */
@@ -238,6 +257,15 @@ int nb_tile_config(int64_t n, int64_t n1, int32_t mode, int32_t law, int32_t *ki
  * autotuner. NB_E_INVAL for a bad mode, law, range, split or height. */
 int nb_tile_override(int64_t n_lo, int64_t n_hi, int32_t mode, int32_t law, int32_t nsplit,
                      int32_t rows);
+
+/* Workspace budget for systems created afterwards (and for nb_scratch_bytes and nb_tile_config):
+ * when a system's split, built-in or overridden, would need more than `bytes` of workspace, the
+ * split is coarsened step by step, first to taller bands (FP32 Kahan mode: 1, 2, then 4 rows),
+ * then to half as many chunks, until the workspace fits or cannot shrink further (the workspace
+ * also holds the sorted state, so a budget below that is never met). 0 (the default) sets no
+ * budget. The split of a system, and with it the order of its sums, is fixed when it is created.
+ * Always NB_OK. */
+int nb_set_workspace_budget(size_t bytes);
 
 /* Launch shape of the force kernel for calls issued afterwards (graphs keep the shape they were
  * captured with): 0 (default) launches one workgroup per work unit and lets the hardware

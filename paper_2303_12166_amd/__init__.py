@@ -188,6 +188,24 @@ def nb_retention(handle: ctypes.c_void_p, stream=None) -> tuple:
     return int(past.value), int(bound.value)
 
 
+def nb_resort(handle: ctypes.c_void_p, stream=None) -> None:
+    """Rebuilds the sorted order from the current positions (synchronises the stream)."""
+    _check(load().nb_resort(handle, _stream(stream)), "nb_resort")
+
+
+def nb_sorted_order(handle: ctypes.c_void_p, stream=None) -> np.ndarray:
+    """The force kernels' sorted slot order: element index per slot, -1 for padding."""
+    lib = load()
+    total = ctypes.c_int64(0)
+    _check(lib.nb_sorted_order(handle, None, 0, ctypes.byref(total), _stream(stream)),
+           "nb_sorted_order")
+    out = np.zeros(max(int(total.value), 1), dtype=np.int32)
+    _check(lib.nb_sorted_order(handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                               int(total.value), ctypes.byref(total), _stream(stream)),
+           "nb_sorted_order")
+    return out[: int(total.value)]
+
+
 def nb_l1_log(handle: ctypes.c_void_p, max_steps: int = NB_L1_LOG_CAP, stream=None) -> np.ndarray:
     out = np.zeros((max(int(max_steps), 1), 4), dtype=np.int32)
     n = ctypes.c_int32(0)
@@ -239,6 +257,11 @@ def nb_graph_launch(graph: ctypes.c_void_p, stream=None) -> None:
 
 def nb_graph_destroy(graph: ctypes.c_void_p) -> None:
     load().nb_graph_destroy(graph)
+
+
+def nb_set_workspace_budget(nbytes: int) -> None:
+    """Workspace budget for systems created afterwards (0: none); see include/nbody.h."""
+    _check(load().nb_set_workspace_budget(int(nbytes)), "nb_set_workspace_budget")
 
 
 def nb_set_force_grid(blocks: int) -> None:

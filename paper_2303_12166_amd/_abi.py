@@ -37,12 +37,15 @@ EXPORTED = (
     "nb_l1_log",
     "nb_nonfinite_async",
     "nb_retention",
+    "nb_sorted_order",
+    "nb_resort",
     "nb_timing_enable",
     "nb_timing_read",
     "nb_timing_reset",
     "nb_tile_config",
     "nb_tile_override",
     "nb_set_force_grid",
+    "nb_set_workspace_budget",
     "nb_valu_probe",
     "nb_graph_create",
     "nb_graph_launch",
@@ -119,6 +122,8 @@ def declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.nb_l1_log.argtypes = [_vp, P(_i32), _i32, P(_i32), _vp]
     lib.nb_nonfinite_async.argtypes = [P(_vp), _i32, P(_i32), _vp]
     lib.nb_retention.argtypes = [_vp, P(_i32), P(_i32), _vp]
+    lib.nb_sorted_order.argtypes = [_vp, P(_i32), _i64, P(_i64), _vp]
+    lib.nb_resort.argtypes = [_vp, _vp]
     lib.nb_timing_enable.argtypes = [_i32]
     lib.nb_timing_read.argtypes = [P(ctypes.c_double), P(_i64)]
     lib.nb_timing_reset.argtypes = []
@@ -126,6 +131,7 @@ def declare(lib: ctypes.CDLL) -> ctypes.CDLL:
                                    P(_i32)]
     lib.nb_tile_override.argtypes = [_i64, _i64, _i32, _i32, _i32, _i32]
     lib.nb_set_force_grid.argtypes = [_i32]
+    lib.nb_set_workspace_budget.argtypes = [ctypes.c_size_t]
     lib.nb_valu_probe.argtypes = [_i32, _i32, _i32, _vp, _vp, P(ctypes.c_double), P(_i64)]
     lib.nb_graph_create.argtypes = [P(_vp), _i32, _i32, _vp, P(_vp)]
     lib.nb_graph_launch.argtypes = [_vp, _vp]

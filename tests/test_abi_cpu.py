@@ -107,6 +107,36 @@ def test_tile_override(nb):
     assert nb.nb_tile_config(100000, 60000, K, P) == before_p
 
 
+def test_workspace_budget_coarsens_the_split(nb):
+    """Over the budget, taller bands come first (FP32 Kahan), then fewer chunks; without a
+    budget the split is the requested one again."""
+    K, F = nb.NB_FP32_KAHAN, nb.NB_FP64
+    n, n1 = 262144, 201650
+    p = _params(nb, n=n, n1=n1)
+    p64 = _params(nb, n=n, n1=n1, mode=F)
+    nb.nb_tile_override(n, n, K, 114, 1)
+    nb.nb_tile_override(n, n, F, 114, 1)
+    try:
+        full, full64 = nb.nb_scratch_bytes(p), nb.nb_scratch_bytes(p64)
+        nb.nb_set_workspace_budget(1_000_000_000)
+        try:
+            cfg = nb.nb_tile_config(n, n1, K)
+            cfg64 = nb.nb_tile_config(n, n1, F)
+            small, small64 = nb.nb_scratch_bytes(p), nb.nb_scratch_bytes(p64)
+        finally:
+            nb.nb_set_workspace_budget(0)
+        assert small <= 1_000_000_000 < full
+        assert cfg["rows"] == 4 and cfg["nsplit"] == 114
+        # the FP64 kernel has one row per band: only its chunk count can shrink, and its
+        # reactions alone (doubles) exceed the budget, so it ends at one chunk
+        assert cfg64["rows"] == 1 and cfg64["nsplit"] == 1 and small64 < full64
+        assert nb.nb_scratch_bytes(p) == full
+        assert nb.nb_tile_config(n, n1, K)["rows"] == 1
+    finally:
+        nb.nb_tile_override(n, n, K, 0, 1)
+        nb.nb_tile_override(n, n, F, 0, 1)
+
+
 # (n_lo, n_hi, mode, law, nsplit, rows)
 @pytest.mark.parametrize("args", [(0, 10, 1, 0, 3, 3), (0, 10, 2, 0, 3, 2), (0, 10, 0, 0, 3, 4),
                                   (0, 10, 7, 0, 3, 1), (10, 0, 1, 0, 3, 1), (0, 10, 1, 0, -1, 1),
@@ -169,6 +199,13 @@ def test_step_static_rejects_bad_arguments(nb):
     many = (ctypes.c_void_p * (nb.NB_STATIC_MAX_SYS + 1))()
     assert lib.nb_step_static(many, nb.NB_STATIC_MAX_SYS + 1, 1, None) == nb.NB_E_LIMIT
     assert "static segment table" in nb.nb_strerror(nb.NB_E_LIMIT)
+
+
+def test_sorted_order_rejects_bad_arguments(nb):
+    lib = nb.load()
+    n = ctypes.c_int64(0)
+    assert lib.nb_sorted_order(None, None, 0, ctypes.byref(n), None) == nb.NB_E_INVAL
+    assert lib.nb_resort(None, None) == nb.NB_E_INVAL
 
 
 def test_strerror_and_version(nb):

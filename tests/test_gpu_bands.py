@@ -146,3 +146,40 @@ def test_band_full_size_sampled_rows(rows):
     scale = np.linalg.norm(ref, axis=1).max()
     err = np.linalg.norm(a[rows_s] - ref, axis=1).max() / scale
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("mode,tol", [("kahan", 1e-5), ("fp64", 1e-12)])
+def test_split_coarsened_by_the_workspace_budget(mode, tol):
+    """A system created under a workspace budget below its requested split's workspace gets a
+    coarser split (taller bands, then fewer chunks) and still oracle parity."""
+    nb = require_gpu()
+    n = 12345
+    ic = synth.make_binary(n, 0.6, seed=9)
+    M = nb.MODES[mode]
+    nb.nb_tile_override(n, n, M, 12, 1)
+    try:
+        req = nb.nb_tile_config(n, ic.n1, M)
+        p = nb.NbParams(n=n, n1=ic.n1, G=ic.G, m=ic.m, dt=1e-4, D1=ic.D1, D2=ic.D2, q=ic.q,
+                        a=ic.a, R2_0=ic.R2, growth_rate=1e-4, growth_on=1, mode=M, law=0, pad=0,
+                        eps=0.0, gamma=0.0, beta=1.0)
+        full = nb.nb_scratch_bytes(p)
+        nb.nb_set_workspace_budget(full * 2 // 3)
+        try:
+            cfg = nb.nb_tile_config(n, ic.n1, M)
+            s = nb.System.from_ic(ic, mode=mode)
+            # the FP32 Kahan split fits; the FP64 one (one row per band) shrinks as far as a
+            # single chunk allows, still above the budget
+            small = nb.nb_scratch_bytes(p)
+            assert small <= full * 2 // 3 if mode == "kahan" else small < full
+        finally:
+            nb.nb_set_workspace_budget(0)
+        assert nb.nb_scratch_bytes(p) == full  # budget lifted: the requested split again
+    finally:
+        nb.nb_tile_override(n, n, M, 0, 1)
+    print_case("budget", mode, req, cfg)
+    assert cfg != req
+    a = s.accelerations()
+    s.close()
+    p64, _ = ic.f32_as_f64()
+    ref = oracle.accel(p64, ic.n1, ic.G, ic.m, ic.D1, ic.D2)
+    assert force_error(a, ref) <= tol

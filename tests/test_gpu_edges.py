@@ -1,6 +1,7 @@
 """Edge cases of the GPU path: an empty system alone and inside a batch, the largest size tried
-(N = 1,048,576, about 26 GB of reaction buffer in Kahan mode) against the oracle on sampled
-rows, and a system whose stars are both a single element."""
+(N = 1,048,576: bands of four tile rows by the built-in rule, about 9.5 GB of workspace in Kahan
+mode) against the oracle on sampled rows, a system whose stars are both a single element, and
+the sorted layout the force kernels work in."""
 
 import numpy as np
 import pytest
@@ -178,3 +179,24 @@ def test_force_timing_counts_exactly_the_timed_launches():
     assert 0.0 < ms < 1000.0
     nb.nb_timing_reset()
     assert nb.nb_timing_read() == (0.0, 0)
+
+
+@pytest.mark.parametrize("n,q", [(3001, 0.3), (700, 0.9), (1, 0.5)])
+def test_sorted_order_is_a_per_star_permutation(n, q):
+    """nb_sorted_order: star 1's elements fill slots [0, n1) and star 2's start at
+    roundup(n1, 256), each exactly once, every other slot is padding (-1), and the slot count is
+    a whole number of 256-slot tiles."""
+    nb = require_gpu()
+    ic = synth.make_binary(n, q, seed=3)
+    print_case("sorted order", n, q)
+    s = nb.System.from_ic(ic, mode="kahan")
+    perm = nb.nb_sorted_order(s.handle, s.stream)
+    s.close()
+    n1 = ic.n1
+    p1 = -(-n1 // 256) * 256
+    n2 = n - n1
+    assert perm.size == p1 + -(-n2 // 256) * 256 and perm.size % 256 == 0
+    assert sorted(perm[:n1].tolist()) == list(range(n1))
+    assert np.all(perm[n1:p1] == -1)
+    assert sorted(perm[p1:p1 + n2].tolist()) == list(range(n1, n))
+    assert np.all(perm[p1 + n2:] == -1)
