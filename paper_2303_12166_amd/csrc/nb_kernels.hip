@@ -718,63 +718,108 @@ void k_force_sym_paper(Launch L)
 }
 
 // a = G m (sum of the element's own chunk partials, then the reactions of every band with a
-// row before the element's tile, in band order), one Kahan sum per component, scattered to the
-// element's own index. KR is the system's band height.
+// row before the element's tile, in band order), scattered to the element's own index. KR is the
+// system's band height. The element's terms (its cj chunk partials, then its ng band reactions)
+// are cut into COMBINE_SEGS contiguous runs, one thread each; a run is a Kahan sum per component
+// in term order, with the three components' loads issued together, eight terms at a time. The
+// runs' results are then added in run order with Kahan compensation by the element's first
+// thread. The order of every addition depends on the system's size alone.
+constexpr int COMBINE_SEGS = 4;
+
 template <int KR>
-__device__ __forceinline__ void combine_tile(const SysDesc &S, int J, int e)
+__device__ __forceinline__ void combine_tile(const SysDesc &S, int J, int e, int k,
+                                             float (*part)[COMBINE_SEGS][TJ])
 {
     const int T = S.ntiles;
     const int slot = J * TJ + e;
     const int idx = S.perm[slot];
-    if (idx < 0) return;
     const float *P = static_cast<const float *>(S.part);
     const float *R = S.react;
     const size_t na = S.nalloc;
     const int own = J / KR;                           // the element's own band
     const int cj = (T - KR * own + S.ch - 1) / S.ch;  // its chunk count
     const int ng = (J + KR - 1) / KR;                 // bands with a row before J
-    float out[3];
-    for (int d = 0; d < 3; ++d) {
-        float sum = 0.f, comp = 0.f;
-        for (int c = 0; c < cj; ++c) kahan_add(sum, comp, P[(size_t)c * 3 * na + d * na + slot]);
-        // bands are read eight at a time (independent loads in flight), then added in band
-        // order; the arithmetic is the same as one band at a time
-        size_t off = 0;
-        size_t len = (size_t)(T - 1) * TJ;
-        int g = 0;
-        for (; g + 8 <= ng; g += 8) {
-            float v[8];
+    const int M = cj + ng;                            // terms
+    const int t0 = (int)(((int64_t)M * k) / COMBINE_SEGS);
+    const int t1 = (int)(((int64_t)M * (k + 1)) / COMBINE_SEGS);
+    float sum[3] = {0.f, 0.f, 0.f}, comp[3] = {0.f, 0.f, 0.f};
+    if (idx >= 0) {
+        int t = t0;
+        // chunk partials
+        for (; t < min(t1, cj); ++t) {
+            const size_t at = (size_t)t * 3 * na + slot;
+            const float vx = P[at], vy = P[at + na], vz = P[at + 2 * na];
+            kahan_add(sum[0], comp[0], vx);
+            kahan_add(sum[1], comp[1], vy);
+            kahan_add(sum[2], comp[2], vz);
+        }
+        // band reactions: band g's block starts at 3 TJ (g (T - 1) - KR g (g - 1) / 2) and holds
+        // three components of (T - KR g - 1) TJ values; the element's value sits at slot -
+        // TJ (KR g + 1) inside each
+        int g = t - cj;
+        const int g1 = t1 - cj;
+        if (g < g1) {
+            size_t off = react_group_offset(g, T, KR);
+            size_t len = (size_t)(T - KR * g - 1) * TJ;
+            for (; g + 8 <= g1; g += 8) {
+                float v[8][3];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                v[q] = R[off + d * len + slot - (size_t)TJ * (KR * (g + q) + 1)];
+                for (int q = 0; q < 8; ++q) {
+                    const size_t at = off + slot - (size_t)TJ * (KR * (g + q) + 1);
+                    v[q][0] = R[at];
+                    v[q][1] = R[at + len];
+                    v[q][2] = R[at + 2 * len];
+                    off += 3 * len;
+                    len -= (size_t)KR * TJ;
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    kahan_add(sum[0], comp[0], v[q][0]);
+                    kahan_add(sum[1], comp[1], v[q][1]);
+                    kahan_add(sum[2], comp[2], v[q][2]);
+                }
+            }
+            for (; g < g1; ++g) {
+                const size_t at = off + slot - (size_t)TJ * (KR * g + 1);
+                kahan_add(sum[0], comp[0], R[at]);
+                kahan_add(sum[1], comp[1], R[at + len]);
+                kahan_add(sum[2], comp[2], R[at + 2 * len]);
                 off += 3 * len;
                 len -= (size_t)KR * TJ;
             }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) kahan_add(sum, comp, v[q]);
         }
-        for (; g < ng; ++g) {
-            kahan_add(sum, comp, R[off + d * len + slot - (size_t)TJ * (KR * g + 1)]);
-            off += 3 * len;
-            len -= (size_t)KR * TJ;
-        }
-        out[d] = sum - comp;
     }
-    const float gm = S.st->gm_f;
-    static_cast<float *>(S.ax)[idx] = gm * out[0];
-    static_cast<float *>(S.ay)[idx] = gm * out[1];
-    static_cast<float *>(S.az)[idx] = gm * out[2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) part[d][k][e] = sum[d] - comp[d];
+    __syncthreads();
+    if (k == 0 && idx >= 0) {
+        float out[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            float s = part[d][0][e], c = 0.f;
+#pragma unroll
+            for (int q = 1; q < COMBINE_SEGS; ++q) kahan_add(s, c, part[d][q][e]);
+            out[d] = s - c;
+        }
+        const float gm = S.st->gm_f;
+        static_cast<float *>(S.ax)[idx] = gm * out[0];
+        static_cast<float *>(S.ay)[idx] = gm * out[1];
+        static_cast<float *>(S.az)[idx] = gm * out[2];
+    }
+    __syncthreads();  // part is rewritten by the block's next tile
 }
 
-__global__ __launch_bounds__(BT) void k_combine_sym(Launch L)
+__global__ __launch_bounds__(BT * COMBINE_SEGS) void k_combine_sym(Launch L)
 {
+    __shared__ float part[3][COMBINE_SEGS][TJ];
+    const int e = threadIdx.x % TJ, k = threadIdx.x / TJ;
     for (int u = blockIdx.x; u < L.total_tunits; u += gridDim.x) {
         const SysDesc &S = L.sys[find_tile_sys(L, u)];
         const int J = u - S.tunit_begin;
         switch (S.rows) {
-        case 1: combine_tile<1>(S, J, threadIdx.x); break;
-        case 2: combine_tile<2>(S, J, threadIdx.x); break;
-        default: combine_tile<4>(S, J, threadIdx.x); break;
+        case 1: combine_tile<1>(S, J, e, k, part); break;
+        case 2: combine_tile<2>(S, J, e, k, part); break;
+        default: combine_tile<4>(S, J, e, k, part); break;
         }
     }
 }
@@ -1589,7 +1634,7 @@ hipError_t launch_combine(const Launch &L, int mode, hipStream_t s)
     if (mode == 0) {
         hipLaunchKernelGGL(k_combine_f32, g, b, 0, s, L);
     } else if (mode == 1) {
-        hipLaunchKernelGGL(k_combine_sym, g, b, 0, s, L);
+        hipLaunchKernelGGL(k_combine_sym, g, dim3(BT * COMBINE_SEGS), 0, s, L);
     } else {
         hipLaunchKernelGGL(k_combine_sym64, g, b, 0, s, L);
     }
