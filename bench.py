@@ -347,6 +347,9 @@ def serving(scale: str) -> dict:
         "sims_per_s_speedup": sb["sims_per_s"] / ss["sims_per_s"],
         "results_identical": same,
         "evicted_nonfinite": server.evicted,
+        "memory": {"peak_footprint_bytes": server.peak_footprint_bytes,
+                   "peak_allocated_bytes": server.peak_allocated_bytes,
+                   "peak_cached_bytes": server.peak_cached_bytes},
     }
 
 

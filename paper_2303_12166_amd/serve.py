@@ -6,7 +6,10 @@ captured HIP graph that holds K leap-frog steps of every active system (one laun
 step over the whole segment table). Between rounds it retires finished systems, admits waiting
 requests first-come first-served while their device footprint fits the memory budget, and builds
 newly admitted systems on a second stream in a worker thread, so admission overlaps the running
-rounds. A request whose footprint exceeds the whole budget is rejected.
+rounds. A request whose footprint exceeds the whole budget is rejected. The budget bounds the
+summed footprint of admitted systems; the server also records PyTorch's peak allocation over the
+run, which the footprints bound (up to the allocator's rounding), and its peak cache, which may
+exceed them when freed blocks of retired systems cannot be reused as they are.
 
 Rounds are queued ``depth`` (default 2) ahead on the compute stream: while one round runs, the
 host picks the next round's systems, builds its graph if needed and queues it, and only then waits
@@ -167,6 +170,12 @@ class BatchServer:
         self.rounds = 0
         self.graphs_built = 0
         self.evicted = 0
+        # memory of the last run: the largest summed footprint admitted at once, and PyTorch's
+        # peak device allocation (live tensors) and peak cache (held blocks) during it, over the
+        # allocation already live when the run started
+        self.peak_footprint_bytes = 0
+        self.peak_allocated_bytes = 0
+        self.peak_cached_bytes = 0
         # pinned host slots for the per-round non-finite counts
         self._flags = torch.zeros(self.max_active, dtype=torch.int32, pin_memory=True)
 
@@ -204,6 +213,7 @@ class BatchServer:
                 sysm = self.build_system(req)
                 sysm.use_on(self.compute)
                 ready.put((req, rec, sysm, None))
+                del sysm  # the main loop owns it now
             except Exception as e:  # reported by the main loop
                 ready.put((req, rec, None, e))
 
@@ -223,6 +233,10 @@ class BatchServer:
         reserved = 0
         in_flight = 0
         graphs = {}  # (request ids of the round's systems, k) -> graph
+        cuda = self.torch.cuda
+        base_alloc, base_cache = cuda.memory_allocated(), cuda.memory_reserved()
+        cuda.reset_peak_memory_stats()
+        self.peak_footprint_bytes = 0
         t0 = time.perf_counter()
 
         def now():
@@ -244,6 +258,7 @@ class BatchServer:
                     req = waiting.popleft()
                     rec = recs[req.rid]
                     reserved += rec.bytes
+                    self.peak_footprint_bytes = max(self.peak_footprint_bytes, reserved)
                     rec.t_admit = now()
                     rec.status = "admitted"
                     in_flight += 1
@@ -257,6 +272,7 @@ class BatchServer:
                     if err is not None:
                         raise err
                     active.append([sysm, rec, req.steps])
+                    sysm = None
                 if not active and not inflight:
                     # idle: wait for an arrival or a system under construction
                     nxt = pending[0].t_arrive - now() if pending else 0.002
@@ -362,6 +378,8 @@ class BatchServer:
                 nb_graph_destroy(g)
             for a in active:
                 a[0].close()
+            self.peak_allocated_bytes = cuda.max_memory_allocated() - base_alloc
+            self.peak_cached_bytes = cuda.max_memory_reserved() - base_cache
         return [recs[r.rid] for r in trace]
 
 

@@ -141,10 +141,14 @@ class System:
         return self.side[: self.n].cpu().numpy()
 
     def close(self):
+        """Destroys the library handle and releases the device tensors (the memory returns to
+        PyTorch's allocator at once, whatever other references to this object remain)."""
         if getattr(self, "handle", None) is not None and self.handle.value:
             self.synchronize()
             nb_destroy(self.handle)
             self.handle = None
+            for name in ("x", "y", "z", "vx", "vy", "vz", "ax", "ay", "az", "side", "_scratch"):
+                setattr(self, name, None)
 
     def __del__(self):
         try:

@@ -100,6 +100,10 @@ def test_server_admission_under_small_budget():
     server = serve.BatchServer(budget_bytes=budget, round_steps=5)
     recs = server.run(trace)
     assert all(r.status == "done" for r in recs)
+    # the footprints bound what was admitted at once, and PyTorch's peak allocation over the
+    # run stays within them up to the allocator's rounding (512 B per tensor, 11 per system)
+    assert 0 < server.peak_footprint_bytes <= budget
+    assert server.peak_allocated_bytes <= server.peak_footprint_bytes + 11 * 512 * len(trace)
     # admissions wait for memory: some request is admitted after an earlier one finished
     done_times = sorted(r.t_done for r in recs)
     assert any(r.t_admit >= done_times[0] for r in recs)
