@@ -181,64 +181,37 @@ def oracle_scaling(cores: int) -> dict:
 def valu_probe() -> dict:
     """Measured issue rates of single VALU instruction streams (lane-instructions per clock per
     CU at the 2.4 GHz peak clock): 2048 blocks of 256 lanes (eight waves per SIMD), eight
-    independent chains per lane."""
+    independent chains per lane. Beside each rate, the shader clock the chip held under that
+    stream (s_memtime against the 100 MHz s_memrealtime counter, over one block's run) and the
+    rate per cycle of that clock."""
     import torch
 
     import paper_2303_12166_amd as nb
 
     sink = torch.zeros(64, dtype=torch.float32, device="cuda")
     blocks = N_CU * 4 * 8 // 4
-    out = {}
+    out, clocks, per_cycle = {}, {}, {}
     for op, name, iters in ((0, "v_fma_f32", 65536), (1, "v_rsq_f32", 16384),
                             (2, "v_rcp_f32", 16384), (3, "3 v_fma_f32 + 1 v_rsq_f32", 16384),
                             (4, "v_fmac_f32", 65536), (5, "v_add_f32", 65536),
-                            (6, "v_mul_f32", 65536), (7, "v_sub_f32 (DPP wave_ror:1 source)", 65536)):
+                            (6, "v_mul_f32", 65536), (7, "v_sub_f32 (DPP wave_ror:1 source)", 65536),
+                            (8, "v_mul_f32 + v_add_f32 in turn", 65536)):
         nb.nb_valu_probe(op, blocks, 64, sink)
         best = None
         for _ in range(3):
-            ms, ops = nb.nb_valu_probe(op, blocks, iters, sink)
+            ms, ops, ratio = nb.nb_valu_probe(op, blocks, iters, sink)
             rate = ops / (ms * 1e-3) / (N_CU * CLOCK_HZ)
-            best = rate if best is None else max(best, rate)
-        out[name] = round(best, 2)
+            if best is None or rate > best[0]:
+                best = (rate, ratio)
+        out[name] = round(best[0], 2)
+        ghz = 0.1 * best[1]
+        clocks[name] = round(ghz, 3)
+        per_cycle[name] = round(best[0] * CLOCK_HZ / (ghz * 1e9), 2) if ghz > 0 else None
     out["unit"] = "lane-instructions per clock per CU (2.4 GHz, 256 CUs)"
     out["published_fma_lanes_per_clk_cu"] = FMA_LANES_PER_CLK_CU
+    out["shader_clock_ghz"] = clocks
+    out["per_cycle_of_shader_clock"] = per_cycle
     return out
-
-
-def issue_model(counters: dict, probe: dict, rows: int, pairs: float, avg_s: float):
-    """Issue-time estimates of the force kernel from its instruction counts per pair (rocprofv3
-    counters by class) and the probe's measured single-stream rate of each class on this part.
-
-    serial_ms: every instruction at its class's rate, one after the other (rotated DPP
-    subtractions, 3 per pair and band of `rows` rows, at the probe's back-to-back DPP rate);
-    mul_trans_ms: the multiplies, FMAs, transcendentals and other non-add VALU instructions
-    alone, that is every add, subtraction and DPP subtraction issued beside them at no cost.
-    A kernel that overlaps the classes runs below serial_ms; mul_trans_ms is a floor only as far
-    as the multiply and transcendental streams do not overlap each other."""
-    need = ("add_f32_lane_instructions_per_pair", "mul_f32_lane_instructions_per_pair",
-            "fma_f32_lane_instructions_per_pair", "trans_lane_instructions_per_pair",
-            "valu_lane_instructions_per_pair")
-    rkeys = ("v_add_f32", "v_mul_f32", "v_rsq_f32", "v_sub_f32 (DPP wave_ror:1 source)")
-    if not probe or avg_s <= 0 or any(counters.get(k) is None for k in need) or \
-            any(not probe.get(k) for k in rkeys):
-        return None
-    add_all = counters["add_f32_lane_instructions_per_pair"]
-    dpp = 3.0 / rows if rows else 0.0
-    add = max(add_all - dpp, 0.0)
-    mul = counters["mul_f32_lane_instructions_per_pair"] + counters[
-        "fma_f32_lane_instructions_per_pair"]
-    trans = counters["trans_lane_instructions_per_pair"]
-    other = max(counters["valu_lane_instructions_per_pair"] - add_all - mul - trans, 0.0)
-    r_add, r_mul, r_trans, r_dpp = (probe[k] for k in rkeys)
-    # CU-clocks per pair; other VALU (integer, moves, selects) priced like a multiply
-    heavy = (mul + other) / r_mul + trans / r_trans
-    serial = add / r_add + dpp / r_dpp + heavy
-    scale = pairs / (N_CU * CLOCK_HZ)
-    return {"per_pair": {"add": round(add, 3), "dpp_sub": round(dpp, 3), "mul_fma": round(mul, 3),
-                         "trans": round(trans, 3), "other": round(other, 3)},
-            "serial_ms": round(serial * scale * 1e3, 3),
-            "mul_trans_ms": round(heavy * scale * 1e3, 3),
-            "measured_ms": round(avg_s * 1e3, 3)}
 
 
 def copy_calibration() -> int:
@@ -753,11 +726,10 @@ def main() -> int:
             if probe and probe.get("v_fma_f32"):
                 roofline["counters"]["valu_issue_frac_of_probe_fma"] = round(
                     rate / (N_CU * CLOCK_HZ) / probe["v_fma_f32"], 4)
-            model = issue_model(counters, probe, cfg["rows"] if kernel.startswith("k_force_sym<")
-                                or kernel.startswith("k_force_sym_paper<") else 0,
-                                evaluated, avg_s)
-            if model:
-                roofline["counters"]["issue_model"] = model
+            for key in ("add_f32", "mul_f32", "fma_f32"):
+                k = key + "_lane_instructions_per_pair"
+                if counters.get(k) is not None:
+                    roofline["counters"][k] = counters[k]
 
     out = {
         "metric": METRIC,

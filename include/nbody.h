@@ -278,13 +278,15 @@ int nb_set_force_grid(int32_t blocks);
  * issue-rate probe of the vector ALU on the current device and stream. Each of blocks x 256 lanes
  * runs iters steps of eight independent dependency chains of one instruction: op 0 v_fma_f32
  * (VOP3), op 1 v_rsq_f32, op 2 v_rcp_f32, op 3 three v_fma_f32 per v_rsq_f32, op 4 v_fmac_f32,
- * op 5 v_add_f32, op 6 v_mul_f32 (VOP2), op 7 v_sub_f32 with a DPP wave-rotation source.
- * *lane_ops receives the
- * lane-instructions executed, *ms the kernel time (HIP events; synchronises `stream`). `sink` is
- * a device buffer of at least 4 bytes that the probe may write (it keeps the chains live).
- * NB_E_INVAL for a bad op, size or buffer. */
+ * op 5 v_add_f32, op 6 v_mul_f32 (VOP2), op 7 v_sub_f32 with a DPP wave-rotation source, op 8
+ * one v_mul_f32 and one v_add_f32 in turn. *lane_ops receives the lane-instructions executed, *ms
+ * the kernel time (HIP events; synchronises `stream`), *clock_ratio the shader-clock cycles
+ * (s_memtime) per tick of the constant-rate counter (s_memrealtime) over block 0's run: with that
+ * counter at 100 MHz the shader clock held under the probe's stream is 0.1 x clock_ratio GHz.
+ * `sink` is a device buffer of at least 32 bytes that the probe writes (bytes 8..23 hold the two
+ * counter spans). NB_E_INVAL for a bad op, size or buffer. */
 int nb_valu_probe(int32_t op, int32_t blocks, int32_t iters, void *sink, void *stream, double *ms,
-                  int64_t *lane_ops);
+                  int64_t *lane_ops, double *clock_ratio);
 
 void nb_destroy(nb_system *s);
 const char *nb_strerror(int status);

@@ -268,15 +268,18 @@ def nb_set_force_grid(blocks: int) -> None:
     _check(load().nb_set_force_grid(int(blocks)), "nb_set_force_grid")
 
 
-def nb_valu_probe(op: int, blocks: int, iters: int, sink, stream=None) -> tuple[float, int]:
-    """(kernel ms, lane-instructions executed) of one vector-ALU issue-rate probe launch;
-    ``sink`` is a device tensor of at least 4 bytes."""
+def nb_valu_probe(op: int, blocks: int, iters: int, sink, stream=None) -> tuple:
+    """(kernel ms, lane-instructions executed, shader-clock cycles per constant-rate counter
+    tick) of one vector-ALU issue-rate probe launch; ``sink`` is a device tensor of at least 32
+    bytes."""
     ms = ctypes.c_double(0.0)
     ops = ctypes.c_int64(0)
+    ratio = ctypes.c_double(0.0)
     _check(load().nb_valu_probe(int(op), int(blocks), int(iters),
                                 ctypes.c_void_p(sink.data_ptr()), _stream(stream),
-                                ctypes.byref(ms), ctypes.byref(ops)), "nb_valu_probe")
-    return float(ms.value), int(ops.value)
+                                ctypes.byref(ms), ctypes.byref(ops), ctypes.byref(ratio)),
+           "nb_valu_probe")
+    return float(ms.value), int(ops.value), float(ratio.value)
 
 
 def nb_destroy(handle: ctypes.c_void_p) -> None:

@@ -132,7 +132,8 @@ def declare(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.nb_tile_override.argtypes = [_i64, _i64, _i32, _i32, _i32, _i32]
     lib.nb_set_force_grid.argtypes = [_i32]
     lib.nb_set_workspace_budget.argtypes = [ctypes.c_size_t]
-    lib.nb_valu_probe.argtypes = [_i32, _i32, _i32, _vp, _vp, P(ctypes.c_double), P(_i64)]
+    lib.nb_valu_probe.argtypes = [_i32, _i32, _i32, _vp, _vp, P(ctypes.c_double), P(_i64),
+                                  P(ctypes.c_double)]
     lib.nb_graph_create.argtypes = [P(_vp), _i32, _i32, _vp, P(_vp)]
     lib.nb_graph_launch.argtypes = [_vp, _vp]
     lib.nb_graph_destroy.argtypes = [_vp]

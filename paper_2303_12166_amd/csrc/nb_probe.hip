@@ -13,11 +13,16 @@ constexpr int PROBE_CHAINS = 8;
 // three v_fma_f32 per v_rsq_f32 (the transcendental and FMA streams interleaved, to see whether
 // they overlap); op 4: v_fmac_f32 (VOP2, accumulating into the chain); op 5: v_add_f32 (VOP2);
 // op 6: v_mul_f32 (VOP2); op 7: v_sub_f32 with a DPP wave-rotation source (the symmetric force
-// kernels' rotated j update). The force kernels' pair loops are mostly VOP2 adds, subtractions,
+// kernels' rotated j update); op 8: one v_mul_f32 and one v_add_f32 chain step in turn (whether an
+// add issues beside a multiply). The force kernels' pair loops are mostly VOP2 adds, subtractions,
 // multiplies and fmac.
 template <int OP>
 __global__ __launch_bounds__(256) void k_valu_probe(float *sink, int iters, float b, float c)
 {
+    // shader-clock and constant-rate counters around block 0's run (the clock the chip holds
+    // under this instruction stream)
+    const unsigned long long c0 = __builtin_amdgcn_s_memtime();
+    const unsigned long long r0 = __builtin_amdgcn_s_memrealtime();
     float v[PROBE_CHAINS];
 #pragma unroll
     for (int k = 0; k < PROBE_CHAINS; ++k) v[k] = 1.0f + 0.001f * (float)(threadIdx.x + k);
@@ -39,6 +44,9 @@ __global__ __launch_bounds__(256) void k_valu_probe(float *sink, int iters, floa
                 v[k] = v[k] + u[k];
             } else if constexpr (OP == 6) {
                 v[k] = v[k] * b;
+            } else if constexpr (OP == 8) {
+                u[k] = u[k] * b;
+                v[k] = v[k] + c;
             } else if constexpr (OP == 7) {
                 // lane l takes lane l - 1's value (wave_ror:1) and subtracts u
                 v[k] = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v[k]), 0x13C, 0xf,
@@ -59,6 +67,13 @@ __global__ __launch_bounds__(256) void k_valu_probe(float *sink, int iters, floa
     // per step, the DPP chain falls by about 2 per step, the mul chain decays slowly towards 0),
     // so the store never happens; it keeps the chains live
     if (!(s < 1.0e30f)) sink[0] = s;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const unsigned long long c1 = __builtin_amdgcn_s_memtime();
+        const unsigned long long r1 = __builtin_amdgcn_s_memrealtime();
+        unsigned long long *clk = reinterpret_cast<unsigned long long *>(sink + 2);
+        clk[0] = c1 - c0;
+        clk[1] = r1 - r0;
+    }
 }
 
 hipError_t launch_valu_probe(int op, float *sink, int blocks, int iters, hipStream_t s)
@@ -74,6 +89,7 @@ hipError_t launch_valu_probe(int op, float *sink, int blocks, int iters, hipStre
     case 5: hipLaunchKernelGGL(k_valu_probe<5>, g, b, 0, s, sink, iters, fb, fc); break;
     case 6: hipLaunchKernelGGL(k_valu_probe<6>, g, b, 0, s, sink, iters, fb, fc); break;
     case 7: hipLaunchKernelGGL(k_valu_probe<7>, g, b, 0, s, sink, iters, fb, fc); break;
+    case 8: hipLaunchKernelGGL(k_valu_probe<8>, g, b, 0, s, sink, iters, fb, fc); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -1109,9 +1109,9 @@ int nb_sorted_order(nb_system *s, int32_t *out_host, int64_t cap, int64_t *n_out
 }
 
 int nb_valu_probe(int32_t op, int32_t blocks, int32_t iters, void *sink, void *stream,
-                  double *ms, int64_t *lane_ops)
+                  double *ms, int64_t *lane_ops, double *clock_ratio)
 {
-    if (op < 0 || op > 7 || blocks < 1 || iters < 1 || !sink || !ms || !lane_ops)
+    if (op < 0 || op > 8 || blocks < 1 || iters < 1 || !sink || !ms || !lane_ops || !clock_ratio)
         return NB_E_INVAL;
     int device = -1;
     NB_TRY(hipGetDevice(&device));
@@ -1134,8 +1134,12 @@ int nb_valu_probe(int32_t op, int32_t blocks, int32_t iters, void *sink, void *s
     (void)hipEventDestroy(b);
     if (rc != NB_OK) return rc;
     *ms = t;
-    // eight chains per lane; op 3 issues three FMAs and one reciprocal square root per chain step
-    *lane_ops = (int64_t)blocks * 256 * (int64_t)iters * 8 * (op == 3 ? 4 : 1);
+    uint64_t clk[2] = {0, 0};
+    NB_TRY(hipMemcpy(clk, static_cast<char *>(sink) + 8, sizeof clk, hipMemcpyDeviceToHost));
+    *clock_ratio = clk[1] > 0 ? (double)clk[0] / (double)clk[1] : 0.0;
+    // eight chains per lane; op 3 issues three FMAs and one reciprocal square root per chain
+    // step, op 8 a multiply and an add
+    *lane_ops = (int64_t)blocks * 256 * (int64_t)iters * 8 * (op == 3 ? 4 : (op == 8 ? 2 : 1));
     return NB_OK;
 }
 
