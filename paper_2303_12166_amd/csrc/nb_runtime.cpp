@@ -116,13 +116,14 @@ TileCfg tile_config(int64_t n, int64_t n1, int mode, int law)
     int ns = 1, rows = 1;
     size_t budget = 0;
     if (mode != NB_FP32_PLAIN && c.ntiles > 0) {
-        // built-in rule: about 65536 work units, chunks of 2..16 tiles; under the contact law
-        // bands of four rows from 256 tiles on (measured faster there, and a quarter of the
-        // reaction partials), one row otherwise
+        // built-in rule: about 65536 work units, chunks of 2..16 tiles; from 256 tiles on,
+        // bands of four rows under the contact law and of two under eqs. (4)-(6) (measured
+        // faster there, with a quarter or half of the reaction partials; the eqs. (4)-(6)
+        // kernel spills at four), one row below
         const int64_t per = (int64_t)c.ntiles * c.n_iblocks / 65536;
         const int tpc = (int)std::min<int64_t>(16, std::max<int64_t>(2, per));
         ns = std::max(1, (c.ntiles + tpc / 2) / tpc);
-        rows = law == NB_LAW_CONTACT && c.ntiles >= 256 ? MAX_BAND : 1;
+        rows = c.ntiles < 256 ? 1 : (law == NB_LAW_CONTACT ? MAX_BAND : 2);
         std::lock_guard<std::mutex> g(g_cfg_mu);
         for (const Override &o : g_overrides) {
             if (o.mode == mode && o.law == law && n >= o.lo && n <= o.hi) {
