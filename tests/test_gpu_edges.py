@@ -81,12 +81,13 @@ def test_largest_size_sampled_rows_kahan():
     assert err <= 1e-5
 
 
-@pytest.mark.parametrize("law", ["contact", "paper"])
+@pytest.mark.parametrize("law", ["contact", "paper", "paper-eps0"])
 @pytest.mark.parametrize("mode", ["kahan", "fp64"])
 def test_coincident_elements(mode, law):
     """Distinct elements at exactly the same position (in different tiles and in the same tile):
     the pair has d = 0 and contributes nothing, as the oracle's r = 0 rule says; nothing becomes
-    non-finite."""
+    non-finite. "paper-eps0" takes eqs. (4)-(6) without softening, where the pair scalar of
+    coincident elements is largest."""
     nb = require_gpu()
     ic = synth.with_velocity_noise(synth.make_binary(1500, 0.5, seed=5), 0.05, 1005)
     p, v = ic.f32()
@@ -94,7 +95,9 @@ def test_coincident_elements(mode, law):
     p[700] = p[3]        # same star, far apart in the sorted order
     p[1400] = p[1401]    # donor, neighbours
     p[1100] = p[10]      # across the stars' index ranges
-    kw = synth.paper_law_params(ic) if law == "paper" else {}
+    kw = synth.paper_law_params(ic) if law != "contact" else {}
+    if law == "paper-eps0":
+        kw["eps"] = 0.0
     print_case("coincident elements", mode, law)
     cast = np.float64 if mode == "fp64" else np.float32
     s = nb.System(p.astype(cast), v.astype(cast), ic.n1, G=ic.G, m=ic.m, dt=1e-4, D1=ic.D1,
@@ -105,7 +108,7 @@ def test_coincident_elements(mode, law):
     s.close()
     assert np.isfinite(a).all() and d["nonfinite"] == 0
     p64, v64 = p.astype(np.float64), v.astype(np.float64)
-    if law == "paper":
+    if law != "contact":
         ref = oracle.accel_paper(p64, v64, ic.n1, ic.G, ic.m, ic.D1, ic.D2, kw["eps"],
                                  kw["gamma"], kw["beta"])
     else:
