@@ -294,8 +294,9 @@ def served_errors(sample, refs) -> dict:
                       "per size decile", "requests": rows_out, "max": worst}
 
 
-def serving(scale: str) -> dict:
-    """Continuous batching vs one-at-a-time plain solves on one Poisson request trace."""
+def serving(scale: str, sequential: bool = True) -> dict:
+    """Continuous batching vs one-at-a-time plain solves on one Poisson request trace (the
+    batched run alone with sequential=False, e.g. under a kernel trace)."""
     from paper_2303_12166_amd import serve
 
     trace, desc = serving_trace(scale)
@@ -305,6 +306,10 @@ def serving(scale: str) -> dict:
     batched = server.run(trace, log=log if scale == "full" else None)
     log("batched run %.1f s (%d rounds, %d graphs)" % (time.perf_counter() - t0, server.rounds,
                                                       server.graphs_built))
+    if not sequential:
+        return {"trace": desc, "requests": len(trace), "budget_bytes": budget,
+                "round_steps": server.round_steps, "rounds": server.rounds,
+                "batched": serve.summarize(batched), "evicted_nonfinite": server.evicted}
     t0 = time.perf_counter()
     seq = serve.run_sequential(trace, log=log if scale == "full" else None)
     log("sequential run %.1f s" % (time.perf_counter() - t0))
@@ -549,6 +554,8 @@ def main() -> int:
                     help="serving measurement added to the main line: 'full' (default) the "
                          "256-request trace (Poisson 20/s, N 4096..131072, 500 steps), 'small' a "
                          "48-request trace (N 4096..32768, 200 steps), 'none' no serving")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="with --serve-only: the batched run alone (no one-at-a-time baseline)")
     ap.add_argument("--serve-only", action="store_true",
                     help="print only the serving measurement (--serve picks the trace)")
     ap.add_argument("--precision-study", action="store_true",
@@ -604,7 +611,8 @@ def main() -> int:
 
         nb.load()
         torch.cuda.set_device(0)
-        res = serving("small" if args.serve == "small" else "full")
+        res = serving("small" if args.serve == "small" else "full",
+                      sequential=not args.no_sequential)
         print(json.dumps({
             "metric": METRIC, "value": res["batched"]["sims_per_s"], "unit": "sims/s",
             "n_gpus": 1, "higher_is_better": True, "vs_baseline": None, "dtype": "f32",
