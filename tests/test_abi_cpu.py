@@ -107,6 +107,25 @@ def test_tile_override(nb):
     assert nb.nb_tile_config(100000, 60000, K, P) == before_p
 
 
+def test_built_in_split_above_the_tuned_range(nb):
+    """Above the tuned table's sizes the built-in rule applies: bands of four tile rows under the
+    contact law and of two under eqs. (4)-(6) in the FP32 Kahan mode (from 256 tiles on), one row
+    in the FP64 mode."""
+    import json
+
+    from paper_2303_12166_amd.autotune import TABLE_PATH
+
+    with open(TABLE_PATH) as f:
+        tables = json.load(f)["tables"]
+    n, n1 = 1048576, 582542
+    assert all(b["n_hi"] < n for t in tables.values() for b in t["buckets"])
+    K, F, P = nb.NB_FP32_KAHAN, nb.NB_FP64, nb.NB_LAW_PAPER
+    assert nb.nb_tile_config(n, n1, K)["rows"] == 4
+    assert nb.nb_tile_config(n, n1, K, P)["rows"] == 2
+    assert nb.nb_tile_config(n, n1, F)["rows"] == 1
+    assert nb.nb_tile_config(n, n1, F, P)["rows"] == 1
+
+
 def test_workspace_budget_coarsens_the_split(nb):
     """Over the budget, taller bands come first (FP32 Kahan), then fewer chunks; without a
     budget the split is the requested one again."""
