@@ -57,7 +57,13 @@ def lib_path() -> str:
 
 
 def load() -> ctypes.CDLL:
-    """Loads libnbody.so (built in-tree by ``python -m paper_2303_12166_amd.build``)."""
+    """Loads libnbody.so (built in-tree by ``python -m paper_2303_12166_amd.build``).
+
+    PyTorch is imported first. Its bundled HIP runtime and the ROCm one that libnbody.so was
+    linked against carry the same soname (libamdhip64.so.7), so with PyTorch's already in the
+    process the library binds to it and shares its device, memory and streams. Loaded the other
+    way round, the process would hold two HIP runtimes, and the library's would find no device
+    once PyTorch's had taken it."""
     global _lib
     if _lib is not None:
         return _lib
@@ -67,6 +73,8 @@ def load() -> ctypes.CDLL:
                 raise LibraryMissing(
                     "libnbody.so is not built (%s); run python -m paper_2303_12166_amd.build"
                     % _abi.LIB_PATH)
+            import torch  # noqa: F401  (its HIP runtime must be the process's one)
+
             _lib = _abi.declare(ctypes.CDLL(_abi.LIB_PATH))
     # measured j-split table for this GPU (see autotune.py); the built-in rule otherwise
     from .autotune import apply_saved

@@ -107,6 +107,24 @@ def test_tile_override(nb):
     assert nb.nb_tile_config(100000, 60000, K, P) == before_p
 
 
+def test_library_shares_the_hip_runtime_of_pytorch():
+    """Loaded before PyTorch is imported, libnbody.so still binds to PyTorch's HIP runtime: the
+    process maps one libamdhip64, not a second copy from the ROCm installation (whose runtime
+    would find no device next to PyTorch's)."""
+    import subprocess
+    import sys
+
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_2303_12166_amd as nb\n"
+            "nb.load()\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip() == "1"
+
+
 def test_built_in_split_above_the_tuned_range(nb):
     """Above the tuned table's sizes the built-in rule applies: bands of four tile rows under the
     contact law and of two under eqs. (4)-(6) in the FP32 Kahan mode (from 256 tiles on), one row
