@@ -344,6 +344,13 @@ __device__ __forceinline__ float wave_ror1(float v)
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), DPP_WAVE_ROR1, 0xf, 0xf, true));
 }
 
+// The same move through the LDS crossbar (ds_bpermute, no LDS storage): addr = 4 ((l - 1) mod 64)
+// in lane l.
+__device__ __forceinline__ float xbar_ror1(float v, int addr)
+{
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+
 // A value that is the same in every lane, moved to a scalar register.
 __device__ __forceinline__ float wave_uniform(float v)
 {
@@ -464,14 +471,22 @@ __device__ __forceinline__ void sym_tile(const float4 *__restrict__ sj,
                                          const LawF (&K)[KR], float *rwx, float *rwy, float *rwz,
                                          int lane, int nact)
 {
-    // Row 0 carries the rotation of the j sums: a_j <- rotate(a_j) - p with p = s d kept as an
-    // operand of its own, so that the rotation folds into the subtraction (a VOP2 instruction
-    // with a DPP source; a fused multiply-add cannot take one). The other rows add s d to both
-    // sums with fused multiply-adds: two instructions per component instead of three.
+    // The j sums move one lane per step (lane l takes lane l - 1's sums). With one row per band
+    // the move folds into row 0's update, a_j <- rotate(a_j) - p with p = s d kept as an operand
+    // of its own (a VOP2 subtraction with a DPP source; a fused multiply-add cannot take one).
+    // The other rows add s d to both sums with fused multiply-adds: two instructions per
+    // component instead of three. In taller bands (four rows under the contact law, two or more
+    // under eqs. (4)-(6)) the sums of each j group move through the LDS crossbar (ds_bpermute)
+    // after the group's last row instead, off the vector ALU, and row 0 takes the FMA form too
+    // (measured 6 % faster at four rows under the contact law, 7.5 % at two under eqs. 4-6).
+    // Under the contact law at two rows the DPP form measured 0.5 % faster (its pair code is
+    // the shorter), and at one row three crossbar moves per pair saturate the LDS (half speed).
 #pragma clang fp contract(off)
+    constexpr bool XBAR = LAW == 0 ? KR >= 4 : KR >= 2;
     const float eps = 1.0e-24f;
     float ajx[4] = {0.f, 0.f, 0.f, 0.f}, ajy[4] = {0.f, 0.f, 0.f, 0.f};
     float ajz[4] = {0.f, 0.f, 0.f, 0.f};
+    const int rot_addr = ((lane + 63) & 63) << 2;  // byte address of lane l - 1 (mod 64)
     for (int st = 0; st < 64; ++st) {
         const int e = (lane - st) & 63;
 #pragma unroll
@@ -487,17 +502,11 @@ __device__ __forceinline__ void sym_tile(const float4 *__restrict__ sj,
                 const float dz = P.z - B.z[r];
                 const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps)));
                 const float s = pair_s<LAW, NEAR>(r2, dx, dy, dz, Vj, B.v[r], K[r]);
-                if (r == 0) {
+                if (!XBAR && r == 0) {
                     const float px = s * dx, py = s * dy, pz = s * dz;
-                    if constexpr (LAW == 0 || KR == 1) {
-                        B.ax[r] += px;
-                        B.ay[r] += py;
-                        B.az[r] += pz;
-                    } else {  // measured 1.8 % faster under eqs. (4)-(6) at two rows
-                        B.ax[r] = fmaf(s, dx, B.ax[r]);
-                        B.ay[r] = fmaf(s, dy, B.ay[r]);
-                        B.az[r] = fmaf(s, dz, B.az[r]);
-                    }
+                    B.ax[r] += px;
+                    B.ay[r] += py;
+                    B.az[r] += pz;
                     ajx[g] = wave_ror1(ajx[g]) - px;
                     ajy[g] = wave_ror1(ajy[g]) - py;
                     ajz[g] = wave_ror1(ajz[g]) - pz;
@@ -512,18 +521,24 @@ __device__ __forceinline__ void sym_tile(const float4 *__restrict__ sj,
                 // contact law: keep each pair's instructions together. Left free, the scheduler
                 // gathers the twelve rotated updates of a step at its end, and back-to-back DPP
                 // subtractions issue at about a third of the rate of plain ones (measured 11 %
-                // slower at one row per band). The eqs. (4)-(6) loop measured 3.5 % faster
-                // without the barrier.
+                // slower at one row per band; with the crossbar form at four rows 1.5 % slower).
+                // The eqs. (4)-(6) loop measured 3.5 % faster without the barrier.
                 if constexpr (LAW == 0) __builtin_amdgcn_sched_barrier(0);
+            }
+            if constexpr (XBAR) {
+                ajx[g] = xbar_ror1(ajx[g], rot_addr);
+                ajy[g] = xbar_ror1(ajy[g], rot_addr);
+                ajz[g] = xbar_ror1(ajz[g], rot_addr);
             }
         }
     }
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-        // one more rotation brings element l's sum back to lane l
-        rwx[g * 64 + lane] = wave_ror1(ajx[g]);
-        rwy[g * 64 + lane] = wave_ror1(ajy[g]);
-        rwz[g * 64 + lane] = wave_ror1(ajz[g]);
+        // element l's sum back in lane l: one more rotation after the last step (the crossbar
+        // form did it already)
+        rwx[g * 64 + lane] = XBAR ? ajx[g] : wave_ror1(ajx[g]);
+        rwy[g * 64 + lane] = XBAR ? ajy[g] : wave_ror1(ajy[g]);
+        rwz[g * 64 + lane] = XBAR ? ajz[g] : wave_ror1(ajz[g]);
     }
 }
 
