@@ -162,7 +162,7 @@ def tune(keys=KEYS, q: float = 0.5, repeats: int = 4, max_n: int = 262144,
     import torch
 
     table = {"arch": torch.cuda.get_device_properties(0).gcnArchName.split(":")[0],
-             "library_version": nb_version(), "tables": {}}
+             "library_version": nb_version(), "budget_bytes": int(budget), "tables": {}}
     for key in keys:
         table["tables"][key] = tune_key(key, q, repeats, max_n, budget, log)
     return table
