@@ -325,11 +325,11 @@ void k_force_f32(Launch L)
 // block's four waves keeps one i element of every row of the band, at the same position in each
 // row. A tile's 256 j elements are taken as four groups of 64. At step s (0..63) lane l meets
 // element (l - s) mod 64 of each group: its position is read from LDS once at that rotating
-// offset and paired with the lane's KR i elements, and the j accumulator travels with it, moved
-// one lane per step by a DPP wave rotation fused into the first row's update
-// a_j <- rotate(a_j) - s (r_j - r_i); the other rows subtract their terms in row order. After 64
-// steps (and one last rotation) every lane holds the summed reaction of the wave's 64 KR i
-// elements on its own j. The waves' sums are added in wave order and stored once per
+// offset and paired with the lane's KR i elements, and the j accumulator travels with it, one
+// lane per step: in short bands by a DPP wave rotation fused into the first row's update
+// a_j <- rotate(a_j) - s (r_j - r_i), in tall ones through the LDS crossbar after the group's
+// last row (see sym_tile); the rows add their terms in row order. After 64 steps and the last
+// move every lane holds the summed reaction of the wave's 64 KR i elements on its own j. The waves' sums are added in wave order and stored once per
 // (group, tile): a band of KR rows stores 1/KR of the reaction blocks of single rows. Tiles inside
 // the band are split by row: tile KR g + k is one-sided for row k, full for the rows before it and
 // skipped by the rows after it. k_combine_sym adds, per element, its own row's chunk partials and

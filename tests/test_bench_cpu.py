@@ -45,3 +45,15 @@ def test_served_sample_takes_one_request_per_size_decile():
     for d, r in enumerate(sample):  # each pick lies inside its own tenth of the sizes
         assert all_n[d * 256 // 10] <= r.n <= all_n[(d + 1) * 256 // 10 - 1]
     assert len({r.rid for r in sample}) == 10
+
+
+def test_kernel_hash_ignores_comments_only():
+    """The counter records are keyed by a hash of the kernels' code: comments and layout may
+    change without invalidating them, any change of code may not."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    src = "int f(int a) {\n    // add one\n    return a + 1; /* done */\n}\n"
+    assert bench.code_text(src) == bench.code_text("int f(int a) { return a + 1; }")
+    assert bench.code_text(src) != bench.code_text(src.replace("a + 1", "a + 2"))
+    assert bench.code_text(src) != bench.code_text(src.replace("// add one", "a = 0;"))
