@@ -329,9 +329,9 @@ void k_force_f32(Launch L)
 // lane per step: in short bands by a DPP wave rotation fused into the first row's update
 // a_j <- rotate(a_j) - s (r_j - r_i), in tall ones through the LDS crossbar after the group's
 // last row (see sym_tile); the rows add their terms in row order. After 64 steps and the last
-// move every lane holds the summed reaction of the wave's 64 KR i elements on its own j. The waves' sums are added in wave order and stored once per
-// (group, tile): a band of KR rows stores 1/KR of the reaction blocks of single rows. Tiles inside
-// the band are split by row: tile KR g + k is one-sided for row k, full for the rows before it and
+// move every lane holds the summed reaction of the wave's 64 KR i elements on its own j. The
+// waves' sums are added in wave order and stored once per (group, tile): a band of KR rows
+// stores 1/KR of the reaction blocks of single rows. Tiles inside the band are split by row: tile KR g + k is one-sided for row k, full for the rows before it and
 // skipped by the rows after it. k_combine_sym adds, per element, its own row's chunk partials and
 // then the reactions of every group with a row before the element's tile, in group order, with
 // Kahan compensation. The order of every sum is fixed by the system's own size, so results do not
