@@ -318,24 +318,25 @@ void k_force_f32(Launch L)
 
 // ------------------------------------------------------------------ FP32 symmetric force kernel
 //
-// Newton's third law halves the pair work: the pair (i, j) with i in tile I and j in a later tile
-// J > I is evaluated once. The tile rows are taken in groups ("row bands") of KR consecutive rows
-// (KR = 1, 2 or 4, chosen per system size): a work unit is group g, rows I = KR g .. KR g + KR - 1,
-// against chunk c of its tiles, a run of `ch` tiles starting at KR g + c ch. Each lane of the
-// block's four waves keeps one i element of every row of the band, at the same position in each
-// row. A tile's 256 j elements are taken as four groups of 64. At step s (0..63) lane l meets
-// element (l - s) mod 64 of each group: its position is read from LDS once at that rotating
-// offset and paired with the lane's KR i elements, and the j accumulator travels with it, one
-// lane per step: in short bands by a DPP wave rotation fused into the first row's update
+// Newton's third law halves the pair work: the pair (i, j) with i in tile I and j in a later
+// tile J > I is evaluated once. The tile rows are taken in groups ("row bands") of KR consecutive
+// rows (KR = 1, 2 or 4, chosen per system size): a work unit is group g, rows I = KR g .. KR g +
+// KR - 1, against chunk c of its tiles, a run of `ch` tiles starting at KR g + c ch. Each lane of
+// the block's four waves keeps one i element of every row of the band, at the same position in
+// each row. A tile's 256 j elements are taken as four groups of 64. At step s (0..63) lane l
+// meets element (l - s) mod 64 of each group: its position is read from LDS once at that
+// rotating offset and paired with the lane's KR i elements, and the j accumulator travels with
+// it, one lane per step: in short bands by a DPP wave rotation fused into the first row's update
 // a_j <- rotate(a_j) - s (r_j - r_i), in tall ones through the LDS crossbar after the group's
 // last row (see sym_tile); the rows add their terms in row order. After 64 steps and the last
 // move every lane holds the summed reaction of the wave's 64 KR i elements on its own j. The
 // waves' sums are added in wave order and stored once per (group, tile): a band of KR rows
-// stores 1/KR of the reaction blocks of single rows. Tiles inside the band are split by row: tile KR g + k is one-sided for row k, full for the rows before it and
-// skipped by the rows after it. k_combine_sym adds, per element, its own row's chunk partials and
-// then the reactions of every group with a row before the element's tile, in group order, with
-// Kahan compensation. The order of every sum is fixed by the system's own size, so results do not
-// depend on scheduling or on the other systems of a launch.
+// stores 1/KR of the reaction blocks of single rows. Tiles inside the band are split by row:
+// tile KR g + k is one-sided for row k, full for the rows before it and skipped by the rows
+// after it. k_combine_sym adds, per element, its own row's chunk partials and then the reactions
+// of every group with a row before the element's tile, in group order, with Kahan compensation.
+// The order of every sum is fixed by the system's own size, so results do not depend on
+// scheduling or on the other systems of a launch.
 
 constexpr int DPP_WAVE_ROR1 = 0x13C;  // lane l receives lane l - 1 (mod 64)
 
