@@ -29,8 +29,10 @@ from . import (LAWS, MODES, NbParams, nb_scratch_bytes, nb_tile_config, nb_tile_
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE_PATH = os.path.join(HERE, "tuning", "gfx950.json")
 
-# bucket edges (inclusive ranges) covering 4096 .. 524288 elements, factor 2 apart
-EDGES = [4096, 8192, 16384, 32768, 65536, 131072, 262144, 524288]
+# bucket edges (inclusive ranges) covering 4096 .. 524288 elements: a factor sqrt(2) apart up to
+# 262144 (each bucket is tuned at its geometric middle, so no size is more than 2^(1/4) from the
+# size its split was measured at), then one bucket up to 524287 tuned at 262144
+EDGES = [int(64 * round(4096 * 2 ** (k / 2) / 64)) for k in range(13)] + [524288]
 CHUNKS = (1, 2, 4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256)
 ROWS = {"kahan": (1, 2, 4), "fp64": (1,)}
 # table keys: "<mode>" for the contact law, "<mode>:paper" for eqs. (4)-(6)
