@@ -7,7 +7,9 @@ combine) and, in the FP32 Kahan mode, the band height (tile rows whose pairs one
 together: taller bands store fewer reaction partials and stage each j tile once for more rows,
 at fewer waves per SIMD). For each precision mode, element law and size bucket the tuner times
 one whole force evaluation (gather, force kernel and combine) for every candidate (rows, chunks)
-on a seeded two-star system and keeps the fastest; ``apply`` installs the table through
+on a seeded two-star system and keeps the fastest (the candidates within 2 % of the first pass's
+best are timed again in five interleaved rounds, and the best median wins); ``apply`` installs
+the table through
 ``nb_tile_override``, so the choice stays a function of the mode, law and system size alone (a
 system gets the same split alone and in a batch). A workspace budget can exclude candidates whose
 ``nb_scratch_bytes`` exceeds it.
@@ -21,6 +23,7 @@ import argparse
 import json
 import math
 import os
+import statistics
 import sys
 
 from . import (LAWS, MODES, NbParams, nb_scratch_bytes, nb_tile_config, nb_tile_override,
@@ -34,6 +37,7 @@ TABLE_PATH = os.path.join(HERE, "tuning", "gfx950.json")
 # size its split was measured at), then one bucket up to 524287 tuned at 262144
 EDGES = [int(64 * round(4096 * 2 ** (k / 2) / 64)) for k in range(13)] + [524288]
 CHUNKS = (1, 2, 4, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256)
+REFINE_FRAC, REFINE_ROUNDS = 0.02, 5
 ROWS = {"kahan": (1, 2, 4), "fp64": (1,)}
 # table keys: "<mode>" for the contact law, "<mode>:paper" for eqs. (4)-(6)
 KEYS = ("kahan", "kahan:paper", "fp64", "fp64:paper")
@@ -148,14 +152,37 @@ def tune_key(key: str, q: float = 0.5, repeats: int = 4, max_n: int = 262144,
                     timings["%d:%d" % (rows, ns)] = _time_forces(ic, mode, law_kw, repeats)
                 finally:
                     nb_tile_override(n, n, M, 0, 1, law=W)
-        best = min(timings, key=timings.get)
+        # the candidates within REFINE_FRAC of the fastest are timed again in interleaved rounds
+        # (a first pass of a few evaluations each cannot tell splits 1 % apart); the best median
+        # over the rounds wins
+        first = min(timings.values())
+        close = sorted(k for k, v in timings.items() if v <= first * (1.0 + REFINE_FRAC))
+        refined = {}
+        if len(close) > 1:
+            rounds = {k: [] for k in close}
+            for _ in range(REFINE_ROUNDS):
+                for k in close:
+                    rows, ns = (int(v) for v in k.split(":"))
+                    nb_tile_override(n, n, M, ns, rows, law=W)
+                    try:
+                        rounds[k].append(_time_forces(ic, mode, law_kw, 2 * repeats))
+                    finally:
+                        nb_tile_override(n, n, M, 0, 1, law=W)
+            refined = {k: statistics.median(v) for k, v in rounds.items()}
+            best = min(refined, key=refined.get)
+        else:
+            best = close[0]
         rows, ns = (int(v) for v in best.split(":"))
-        log("%s bucket [%d, %d] tuned at n=%d: rows %d nsplit %d (%.3f ms); %s" % (
-            key, lo, hi, n, rows, ns, timings[best],
-            " ".join("%s=%.3f" % (k, v) for k, v in sorted(timings.items()))))
+        ms = refined.get(best, timings[best])
+        log("%s bucket [%d, %d] tuned at n=%d: rows %d nsplit %d (%.3f ms); %s%s" % (
+            key, lo, hi, n, rows, ns, ms,
+            " ".join("%s=%.3f" % (k, v) for k, v in sorted(timings.items())),
+            "; refined " + " ".join("%s=%.3f" % (k, v) for k, v in sorted(refined.items()))
+            if refined else ""))
         out["buckets"].append({"n_lo": lo, "n_hi": hi, "n_tuned": n, "rows": rows, "nsplit": ns,
-                               "ms": round(timings[best], 4),
-                               "candidates_ms": {k: round(v, 4) for k, v in timings.items()}})
+                               "ms": round(ms, 4),
+                               "candidates_ms": {k: round(v, 4) for k, v in timings.items()},
+                               "refined_ms": {k: round(v, 4) for k, v in refined.items()}})
     return out
 
 
